@@ -1,0 +1,143 @@
+/*
+ * cavi.h -- C ABI of the MI355X (gfx950) library for the mean-field
+ * variational (CAVI) sweep of the Gaussian mixture model of cell
+ * subpopulations in qPCR expression data.
+ *
+ * Model (the mixture reading of the paper's conjugate-exponential framing,
+ * Section 3.3; priors of the form of eqs 5-7):
+ *   pi ~ Dir(alpha0 1_K);  tau_kg ~ Gamma(a0, rate b0);
+ *   mu_kg | tau_kg ~ N(m0_g, 1/(beta0 tau_kg));
+ *   z_n ~ Cat(pi);  x_ng | z_n = k ~ N(mu_kg, 1/tau_kg).
+ * Variational family (eqs 9 and 13): q = prod_n Cat(z_n | r_n) Dir(pi | alpha)
+ *   prod_kg NormalGamma(mu_kg, tau_kg | m_kg, beta_kg, a_kg, b_kg).
+ * One sweep (eq 12 applied block by block, Section 3.4):
+ *   expectations (eqs 26-31) -> per-row expected log-likelihoods under every
+ *   subpopulation -> log-sum-exp responsibilities -> sufficient statistics
+ *   (weighted counts, sums and sums of squares per subpopulation and gene)
+ *   -> conjugate updates (forms of eqs 16, 17 and 24) -> the lower bound
+ *   (eqs 10-11).
+ *
+ * Conventions
+ *   - Every function returns cavi_status; nothing throws across the ABI.
+ *     On failure cavi_last_error() (thread-local) holds a message.
+ *   - Data X is FP32, row-major N x G, in DEVICE memory, caller-owned; it must
+ *     stay alive and unchanged until the handle is destroyed.  The library
+ *     never copies or frees it.  It must be 16-byte aligned.
+ *   - State arrays passed to set/get are HOST memory, FP64, caller-owned:
+ *     alpha[K], and m, beta, a, b as K x G arrays, k-major (index k*G + g).
+ *   - All work is enqueued on the stream given at creation (a hipStream_t
+ *     passed as void*, NULL = the default stream).  Functions that return
+ *     results to the host (get_*, sweep with an ELBO buffer, run) synchronise
+ *     that stream.  A handle is not thread-safe.
+ *   - Workspace: pass device memory of at least cavi_workspace_bytes() bytes
+ *     (256-byte aligned), or NULL to let the library allocate (and free on
+ *     destroy).
+ *   - Determinism: results are bitwise reproducible run to run for the same
+ *     inputs, shapes and library build.  The reduction over rows is defined
+ *     over fixed 2048-row chunks combined in a fixed order.
+ *   - Limits: 1 <= K <= 64, 1 <= G <= 512, K*G <= 4096, K <= N < 2^31.
+ */
+#ifndef CAVI_H
+#define CAVI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CAVI_OK = 0,
+    CAVI_E_INVAL = 1,   /* bad argument (shape, pointer, alignment, limit) */
+    CAVI_E_NOMEM = 2,   /* workspace too small or allocation failed */
+    CAVI_E_HIP = 3,     /* a HIP runtime call failed; message has its text */
+    CAVI_E_NUMERIC = 4, /* non-finite statistic or bound; state rolled back */
+    CAVI_E_NOTCONV = 5, /* max_sweeps reached without convergence (state valid) */
+    CAVI_E_STATE = 6    /* called before a state was initialised or set */
+} cavi_status;
+
+typedef struct cavi_ctx cavi_ctx;
+
+/* Prior hyperparameters (eqs 5-7 in mixture form).  m0 is a HOST array of G
+ * values, or NULL for the per-gene mean of X (computed on the device). */
+typedef struct {
+    double alpha0; /* Dirichlet concentration, > 0 */
+    double beta0;  /* prior precision scale of the means (q0 of eq 6), > 0 */
+    double a0;     /* Gamma shape (eq 5), > 0 */
+    double b0;     /* Gamma rate (eq 5), > 0 */
+    const double *m0;
+} cavi_prior;
+
+/* Defaults: alpha0 = 1 (the Dirichlet(1,1,1) of the synthetic study in
+ * Section 4), beta0 = 0.001 and a0 = b0 = 0.5 (the constants of Section 3.5),
+ * m0 = NULL. */
+cavi_status cavi_prior_default(cavi_prior *prior);
+
+/* Bytes of device workspace needed for one dataset of this shape. */
+cavi_status cavi_workspace_bytes(int64_t N, int32_t G, int32_t K, size_t *bytes);
+
+/* Create a handle over device data X (N x G FP32).  prior may be NULL for the
+ * defaults.  hip_stream is a hipStream_t or NULL.  workspace_dev may be NULL
+ * (library-owned) or caller memory of ws_bytes >= cavi_workspace_bytes().
+ * Errors: CAVI_E_INVAL for N < K, G or K out of limits, null out/x_dev,
+ * misaligned x_dev, non-positive hyperparameters; CAVI_E_NOMEM for a short
+ * workspace; CAVI_E_HIP on a runtime failure. */
+cavi_status cavi_create(cavi_ctx **out, const float *x_dev, int64_t N, int32_t G, int32_t K,
+                        const cavi_prior *prior, void *hip_stream, void *workspace_dev,
+                        size_t ws_bytes);
+
+/* Standard initial state: k-means++ seeds drawn with SplitMix64(seed) from
+ * D^2 weights quantised to integers, hard nearest-seed responsibilities, then
+ * one conjugate update.  Resets the sweep counter. */
+cavi_status cavi_init_standard(cavi_ctx *ctx, uint64_t seed);
+
+/* Inject a state (host FP64 arrays; see Conventions).  Resets the sweep
+ * counter.  CAVI_E_INVAL for non-finite or non-positive alpha/beta/a/b. */
+cavi_status cavi_set_state(cavi_ctx *ctx, const double *alpha, const double *m,
+                           const double *beta, const double *a, const double *b);
+
+/* Copy the current posterior q(pi) q(mu,tau) to host arrays; syncs. */
+cavi_status cavi_get_state(cavi_ctx *ctx, double *alpha, double *m, double *beta, double *a,
+                           double *b);
+
+/* Run exactly n sweeps (no convergence stop).  elbo_host: NULL, or n doubles
+ * receiving the bound after each sweep (then the stream is synchronised).
+ * CAVI_E_NUMERIC if a sweep produced a non-finite value: the state is left
+ * at the last good sweep. */
+cavi_status cavi_sweep(cavi_ctx *ctx, int32_t n, double *elbo_host);
+
+/* Sweep until |L_t - L_{t-1}| <= rel_tol |L_t| (t >= 2 sweeps of this call)
+ * or max_sweeps.  sweeps / elbo (may be NULL) receive the number of sweeps
+ * run and the final bound.  CAVI_E_NOTCONV when max_sweeps is reached. */
+cavi_status cavi_run(cavi_ctx *ctx, int32_t max_sweeps, double rel_tol, int32_t *sweeps,
+                     double *elbo);
+
+/* Responsibilities of the current state (the E-step only), written to caller
+ * device memory r_dev (N x K FP32, row-major).  Enqueued, not synchronised. */
+cavi_status cavi_get_responsibilities(cavi_ctx *ctx, float *r_dev);
+
+/* The per-gene prior centre in use (host array of G doubles). */
+cavi_status cavi_get_prior_mean(cavi_ctx *ctx, double *m0_host);
+
+/* Measurement aid: time reps back-to-back launches of the fused E-step +
+ * statistics kernel (the sweep's dominant kernel) with HIP events on the
+ * handle's stream; *avg_ms receives the mean milliseconds per launch.  Needs
+ * a state; rewrites only the per-chunk partials (the state is unchanged).
+ * Synchronises the stream. */
+cavi_status cavi_profile_estep(cavi_ctx *ctx, int32_t reps, float *avg_ms);
+
+/* Free the handle (and the workspace if library-owned).  NULL is a no-op. */
+cavi_status cavi_destroy(cavi_ctx *ctx);
+
+/* Thread-local text of the last error ("" if none). */
+const char *cavi_last_error(void);
+
+/* Library version string. */
+const char *cavi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CAVI_H */

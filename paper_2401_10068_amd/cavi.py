@@ -1,0 +1,236 @@
+"""Python binding of ``include/cavi.h`` (ctypes; argument marshalling only).
+
+Every function mirrors the C entry point of the same name.  Device arrays are
+``torch`` tensors on a ROCm device (their ``data_ptr()`` is passed through);
+the stream is ``torch.cuda.current_stream()`` unless given.  Every step of the
+sweep runs in ``libcavi.so``; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcavi.so")
+
+CAVI_OK, CAVI_E_INVAL, CAVI_E_NOMEM, CAVI_E_HIP, CAVI_E_NUMERIC, CAVI_E_NOTCONV, CAVI_E_STATE = range(7)
+_NAMES = {0: "CAVI_OK", 1: "CAVI_E_INVAL", 2: "CAVI_E_NOMEM", 3: "CAVI_E_HIP", 4: "CAVI_E_NUMERIC",
+          5: "CAVI_E_NOTCONV", 6: "CAVI_E_STATE"}
+
+
+class CaviError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class cavi_prior(C.Structure):
+    _fields_ = [("alpha0", C.c_double), ("beta0", C.c_double), ("a0", C.c_double), ("b0", C.c_double),
+                ("m0", C.POINTER(C.c_double))]
+
+
+_lib = None
+
+
+def lib():
+    """Load ``libcavi.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2401_10068_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, st = C.c_void_p, C.POINTER(C.c_double), C.c_int
+        sig = {
+            "cavi_prior_default": (st, [C.POINTER(cavi_prior)]),
+            "cavi_workspace_bytes": (st, [C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+            "cavi_create": (st, [C.POINTER(vp), vp, C.c_int64, C.c_int32, C.c_int32, C.POINTER(cavi_prior), vp, vp,
+                                 C.c_size_t]),
+            "cavi_init_standard": (st, [vp, C.c_uint64]),
+            "cavi_set_state": (st, [vp, dp, dp, dp, dp, dp]),
+            "cavi_get_state": (st, [vp, dp, dp, dp, dp, dp]),
+            "cavi_sweep": (st, [vp, C.c_int32, dp]),
+            "cavi_run": (st, [vp, C.c_int32, C.c_double, C.POINTER(C.c_int32), dp]),
+            "cavi_get_responsibilities": (st, [vp, vp]),
+            "cavi_get_prior_mean": (st, [vp, dp]),
+            "cavi_profile_estep": (st, [vp, C.c_int32, C.POINTER(C.c_float)]),
+            "cavi_destroy": (st, [vp]),
+            "cavi_last_error": (C.c_char_p, []),
+            "cavi_version": (C.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != CAVI_OK:
+        raise CaviError(status, lib().cavi_last_error().decode())
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _stream_ptr(stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+# ----------------------------------------------------------------------------- raw entry points
+def cavi_version() -> str:
+    return lib().cavi_version().decode()
+
+
+def cavi_last_error() -> str:
+    return lib().cavi_last_error().decode()
+
+
+def cavi_prior_default() -> cavi_prior:
+    p = cavi_prior()
+    _check(lib().cavi_prior_default(C.byref(p)))
+    return p
+
+
+def cavi_workspace_bytes(N: int, G: int, K: int) -> int:
+    n = C.c_size_t(0)
+    _check(lib().cavi_workspace_bytes(int(N), int(G), int(K), C.byref(n)))
+    return int(n.value)
+
+
+def cavi_create(x, K: int, prior: cavi_prior | None = None, stream=None, workspace=None):
+    """Handle over the device tensor ``x`` (N x G float32, contiguous)."""
+    import torch
+
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 and x.dim() == 2
+            and x.is_contiguous()):
+        raise ValueError("x must be a contiguous 2-D float32 tensor on the GPU")
+    N, G = x.shape
+    h = C.c_void_p()
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = C.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
+    _check(lib().cavi_create(C.byref(h), C.c_void_p(x.data_ptr()), int(N), int(G), int(K),
+                             C.byref(prior) if prior is not None else None, _stream_ptr(stream), ws_ptr, ws_bytes))
+    return h
+
+
+def cavi_init_standard(h, seed: int):
+    _check(lib().cavi_init_standard(h, C.c_uint64(seed)))
+
+
+def cavi_set_state(h, alpha, m, beta, a, b):
+    arrs = [np.ascontiguousarray(v, dtype=np.float64) for v in (alpha, m, beta, a, b)]
+    _check(lib().cavi_set_state(h, *[_dp(v) for v in arrs]))
+
+
+def cavi_get_state(h, K: int, G: int):
+    alpha = np.zeros(K)
+    m, beta, a, b = (np.zeros((K, G)) for _ in range(4))
+    _check(lib().cavi_get_state(h, _dp(alpha), _dp(m), _dp(beta), _dp(a), _dp(b)))
+    return alpha, m, beta, a, b
+
+
+def cavi_sweep(h, n: int, want_elbo: bool = True):
+    elbo = np.zeros(max(n, 1)) if want_elbo else None
+    _check(lib().cavi_sweep(h, int(n), _dp(elbo) if want_elbo else None))
+    return elbo[:n] if want_elbo else None
+
+
+def cavi_run(h, max_sweeps: int, rel_tol: float = 1e-6, raise_notconv: bool = False):
+    """Returns ``(sweeps, elbo, converged)``."""
+    sw = C.c_int32(0)
+    el = C.c_double(0.0)
+    st = lib().cavi_run(h, int(max_sweeps), float(rel_tol), C.byref(sw), C.byref(el))
+    if st == CAVI_E_NOTCONV and not raise_notconv:
+        return sw.value, el.value, False
+    _check(st)
+    return sw.value, el.value, True
+
+
+def cavi_get_responsibilities(h, r):
+    _check(lib().cavi_get_responsibilities(h, C.c_void_p(r.data_ptr())))
+
+
+def cavi_get_prior_mean(h, G: int):
+    m0 = np.zeros(G)
+    _check(lib().cavi_get_prior_mean(h, _dp(m0)))
+    return m0
+
+
+def cavi_profile_estep(h, reps: int) -> float:
+    ms = C.c_float(0.0)
+    _check(lib().cavi_profile_estep(h, int(reps), C.byref(ms)))
+    return float(ms.value)
+
+
+def cavi_destroy(h):
+    if h:
+        _check(lib().cavi_destroy(h))
+
+
+# ----------------------------------------------------------------------------- convenience
+class Cavi:
+    """Owning wrapper: keeps the data tensor and the workspace alive."""
+
+    def __init__(self, x, K: int, alpha0=1.0, beta0=1e-3, a0=0.5, b0=0.5, m0=None, stream=None,
+                 torch_workspace: bool = True):
+        import torch
+
+        self.x = x
+        self.N, self.G = x.shape
+        self.K = int(K)
+        self._m0 = None if m0 is None else np.ascontiguousarray(m0, dtype=np.float64)
+        self.prior = cavi_prior(float(alpha0), float(beta0), float(a0), float(b0),
+                                _dp(self._m0) if self._m0 is not None else None)
+        self.workspace = None
+        if torch_workspace:
+            nbytes = cavi_workspace_bytes(self.N, self.G, self.K)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+        self.h = cavi_create(x, self.K, self.prior, stream, self.workspace)
+
+    def init_standard(self, seed: int = 0):
+        cavi_init_standard(self.h, seed)
+
+    def set_state(self, alpha, m, beta, a, b):
+        cavi_set_state(self.h, alpha, m, beta, a, b)
+
+    def get_state(self):
+        return cavi_get_state(self.h, self.K, self.G)
+
+    def sweep(self, n: int = 1, want_elbo: bool = True):
+        return cavi_sweep(self.h, n, want_elbo)
+
+    def run(self, max_sweeps: int = 10000, rel_tol: float = 1e-6):
+        return cavi_run(self.h, max_sweeps, rel_tol)
+
+    def responsibilities(self):
+        import torch
+
+        r = torch.empty((self.N, self.K), dtype=torch.float32, device=self.x.device)
+        cavi_get_responsibilities(self.h, r)
+        return r
+
+    def profile_estep(self, reps: int = 20) -> float:
+        return cavi_profile_estep(self.h, reps)
+
+    def prior_mean(self):
+        return cavi_get_prior_mean(self.h, self.G)
+
+    def close(self):
+        if self.h:
+            cavi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -129,13 +129,17 @@ class ParamStream:
         while True:
             u = self.uniform()
             n = self.normal()
-            v = (1.0 + c * n) ** 3
+            t = 1.0 + c * n
+            v = t * t * t
             if v > 0.0 and math.log(u) < 0.5 * n * n + d - d * v + d * math.log(v):
                 return d * v / rate
 
     def dirichlet(self, alpha) -> np.ndarray:
-        g = np.array([self.gamma(float(a), 1.0) for a in alpha], dtype=np.float64)
-        return g / g.sum()
+        g = [self.gamma(float(a), 1.0) for a in alpha]
+        s = 0.0
+        for v in g:  # sequential sum, as on the device
+            s += v
+        return np.array([v / s for v in g], dtype=np.float64)
 
 
 # ----------------------------------------------------------------------------- datasets
@@ -235,3 +239,73 @@ def workload(name: str):
     if name == "c3":
         return 10_000_000, Recipe(K=16, G=48, dir_alpha=1.0, overlap_pairs=4, overlap_sd=0.5), 2
     raise KeyError(name)
+
+
+# ----------------------------------------------------------------------------- device twin
+_glib = None
+
+
+def _gpu_lib():
+    global _glib
+    if _glib is None:
+        import ctypes as C
+        import os
+
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcavi_synth.so")
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with `python -m paper_2401_10068_amd.build`")
+        L = C.CDLL(path)
+        vp, d, i32, i64 = C.c_void_p, C.c_double, C.c_int32, C.c_int64
+        L.synth_params.restype = C.c_int
+        L.synth_params.argtypes = [C.c_uint32, i32, i32, vp, i32, i32, d, d, d, d, d, i32, d, vp, vp, vp, vp]
+        L.synth_rows.restype = C.c_int
+        L.synth_rows.argtypes = [C.c_uint32, i32, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, i64, vp]
+        _glib = L
+    return _glib
+
+
+def make_batch_gpu(seed: int, Ns, Ks, recipe: Recipe, ds_offset: int = 0, want_z: bool = False, device="cuda"):
+    """Datasets ``ds_offset + b`` generated on the GPU, rows concatenated.
+
+    Returns ``(x[sum N, G] float32, row_off[B+1] int64, K[B] int32, pi, mu, tau, z)`` as torch
+    tensors on the device (``z`` is None unless asked for).  ``recipe.K`` is ignored; ``Ks`` gives
+    each dataset's K.
+    """
+    import torch
+
+    L = _gpu_lib()
+    Ns = np.asarray(Ns, dtype=np.int64)
+    Ks = np.asarray(Ks, dtype=np.int32)
+    B = Ns.size
+    G = recipe.G
+    Kmax = int(Ks.max())
+    row_off = np.zeros(B + 1, dtype=np.int64)
+    row_off[1:] = np.cumsum(Ns)
+    total = int(row_off[-1])
+    dev = torch.device(device)
+    K_d = torch.from_numpy(Ks).to(dev)
+    off_d = torch.from_numpy(row_off).to(dev)
+    pi = torch.zeros((B, Kmax), dtype=torch.float64, device=dev)
+    mu = torch.zeros((B, Kmax, G), dtype=torch.float64, device=dev)
+    tau = torch.ones((B, Kmax, G), dtype=torch.float64, device=dev)
+    x = torch.empty((total, G), dtype=torch.float32, device=dev)
+    z = torch.empty(total, dtype=torch.int32, device=dev) if want_z else None
+    stream = torch.cuda.current_stream().cuda_stream
+    e = L.synth_params(seed & _MASK, B, ds_offset, K_d.data_ptr(), Kmax, G, recipe.dir_alpha, recipe.mu_lo,
+                       recipe.mu_hi, recipe.tau_shape, recipe.tau_rate, recipe.overlap_pairs, recipe.overlap_sd,
+                       pi.data_ptr(), mu.data_ptr(), tau.data_ptr(), stream)
+    if e:
+        raise RuntimeError(f"synth_params failed: hip error {e}")
+    e = L.synth_rows(seed & _MASK, B, ds_offset, off_d.data_ptr(), K_d.data_ptr(), Kmax, G, pi.data_ptr(),
+                     mu.data_ptr(), tau.data_ptr(), x.data_ptr(), z.data_ptr() if z is not None else None, total,
+                     stream)
+    if e:
+        raise RuntimeError(f"synth_rows failed: hip error {e}")
+    return x, torch.from_numpy(row_off), torch.from_numpy(Ks), pi, mu, tau, z
+
+
+def make_dataset_gpu(seed: int, dataset: int, N: int, recipe: Recipe, want_z: bool = False, device="cuda"):
+    """One dataset on the GPU: ``(x, z, pi, mu, tau)`` (device tensors)."""
+    x, _, _, pi, mu, tau, z = make_batch_gpu(seed, [N], [recipe.K], recipe, ds_offset=dataset, want_z=want_z,
+                                             device=device)
+    return x, z, pi[0], mu[0], tau[0]

@@ -1,0 +1,80 @@
+"""The C ABI library loads and exports every entry point the headers declare;
+argument checks that run before any device call (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2401_10068_amd import cavi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cavi_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(cavi.LIB_PATH):
+        pytest.fail("libcavi.so is not built (run __graft_entry__.build())")
+    return cavi.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared("cavi.h")
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_version_and_empty_error(L):
+    assert cavi.cavi_version().startswith("cavi-gfx950")
+
+
+def test_prior_default_values(L):
+    p = cavi.cavi_prior_default()
+    assert (p.alpha0, p.beta0, p.a0, p.b0) == (1.0, 1e-3, 0.5, 0.5)
+    assert not p.m0
+
+
+def test_workspace_bytes_and_limits(L):
+    n = cavi.cavi_workspace_bytes(1000, 16, 3)
+    assert n > 1000 * 8
+    assert cavi.cavi_workspace_bytes(10**6, 96, 8) > cavi.cavi_workspace_bytes(10**5, 96, 8)
+    for N, G, K in [(10, 4, 0), (10, 4, 65), (10, 0, 2), (10, 513, 2), (10, 128, 33), (2, 4, 3), (2**31, 4, 3)]:
+        with pytest.raises(cavi.CaviError) as e:
+            cavi.cavi_workspace_bytes(N, G, K)
+        assert e.value.status == cavi.CAVI_E_INVAL
+
+
+def _create_raw(L, x_ptr, N, G, K, prior=None, ws=None, ws_bytes=0):
+    h = C.c_void_p()
+    st = L.cavi_create(C.byref(h), C.c_void_p(x_ptr), N, G, K, C.byref(prior) if prior else None, None,
+                       C.c_void_p(ws) if ws else None, ws_bytes)
+    return st, h
+
+
+def test_create_rejects_bad_arguments_before_touching_the_device(L):
+    assert _create_raw(L, 0, 100, 4, 3)[0] == cavi.CAVI_E_INVAL            # NULL data
+    assert _create_raw(L, 0x1004, 100, 4, 3)[0] == cavi.CAVI_E_INVAL       # misaligned
+    assert _create_raw(L, 0x1000, 2, 4, 3)[0] == cavi.CAVI_E_INVAL         # N < K
+    assert _create_raw(L, 0x1000, 100, 4, 0)[0] == cavi.CAVI_E_INVAL       # K = 0
+    bad = cavi.cavi_prior(1.0, -1.0, 0.5, 0.5, None)
+    assert _create_raw(L, 0x1000, 100, 4, 3, prior=bad)[0] == cavi.CAVI_E_INVAL
+    st, _ = _create_raw(L, 0x1000, 100, 4, 3, ws=0x2000, ws_bytes=16)
+    assert st == cavi.CAVI_E_NOMEM
+    assert "workspace" in cavi.cavi_last_error()
+    st = L.cavi_create(None, C.c_void_p(0x1000), 100, 4, 3, None, None, None, 0)
+    assert st == cavi.CAVI_E_INVAL
+
+
+def test_null_handles(L):
+    assert L.cavi_destroy(None) == cavi.CAVI_OK
+    assert L.cavi_sweep(None, 1, None) == cavi.CAVI_E_INVAL
+    assert L.cavi_run(None, 10, 1e-6, None, None) == cavi.CAVI_E_INVAL
+    assert L.cavi_get_state(None, None, None, None, None, None) == cavi.CAVI_E_INVAL
+    assert L.cavi_init_standard(None, 0) == cavi.CAVI_E_INVAL
