@@ -152,7 +152,9 @@ cavi_status cavi_create(cavi_ctx **out, const float *x_dev, int64_t N, int32_t G
         if (((uintptr_t)workspace_dev) & 255) return fail(CAVI_E_INVAL, "workspace is not 256-byte aligned");
     }
     hipError_t e = prepare_kernels();
-    if (e != hipSuccess) return fail(CAVI_E_HIP, "kernel attributes: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return fail(CAVI_E_HIP, "device query: %s", hipGetErrorString(e));
+    s.tile_rows = choose_tile_rows(G, s.kt);
+    if (s.tile_rows < 16) return fail(CAVI_E_INVAL, "G=%d needs more LDS per block than the device has", G);
     cavi_ctx *c = new cavi_ctx;
     c->s = s;
     c->p = Prior{pr.alpha0, pr.beta0, pr.a0, pr.b0};

@@ -22,6 +22,7 @@ namespace {
 constexpr double kLn2Pi = 1.8378770664093454835606594728112;
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr int kMaxItems = kMaxKG / kBlock;  // (k, g) items per thread
+int g_lds_limit = 0;                         // bytes of LDS per block the device allows
 
 __device__ __forceinline__ bool sweep_skipped(const Ctl *c)
 {
@@ -516,10 +517,11 @@ int choose_kt(int K)
 int choose_tile_rows(int G, int kt)
 {
     const size_t per_row = (size_t)(G + 1 + kt + 1) * sizeof(float);
-    const size_t budget = 150 * 1024;
+    // dynamic LDS budget: the device's per-block limit less the static arrays
+    const size_t budget = (size_t)(g_lds_limit > 0 ? g_lds_limit : 65536) - 4096;
     int tr = 256;
-    while (tr > 32 && (size_t)tr * per_row > budget) tr -= 32;
-    return tr;
+    while (tr > 16 && (size_t)tr * per_row > budget) tr -= 16;
+    return (size_t)tr * per_row > budget ? 0 : tr;
 }
 
 static size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -590,19 +592,27 @@ hipError_t prepare_kernels()
 {
     static bool done = false;
     if (done) return hipSuccess;
-    const int lds = 160 * 1024;
-    hipError_t e = hipSuccess;
-    e = hipFuncSetAttribute((const void *)k_estep_stats<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_estep_stats<8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_estep_stats<16>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_estep_stats<32>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_estep_stats<64>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e == hipSuccess) done = true;
-    return e;
+    int dev = 0, per_block = 0, optin = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    (void)hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    (void)hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev);
+    (void)hipGetLastError();
+    g_lds_limit = per_block > optin ? per_block : optin;
+    // Raising the dynamic limit is only needed (and only accepted) where the
+    // opt-in limit exceeds the default one; failures here are not fatal, the
+    // tile size below is chosen against the limit that the device reports.
+    if (optin > per_block) {
+        const int want = optin - 4096;
+        (void)hipFuncSetAttribute((const void *)k_estep_stats<4>, hipFuncAttributeMaxDynamicSharedMemorySize, want);
+        (void)hipFuncSetAttribute((const void *)k_estep_stats<8>, hipFuncAttributeMaxDynamicSharedMemorySize, want);
+        (void)hipFuncSetAttribute((const void *)k_estep_stats<16>, hipFuncAttributeMaxDynamicSharedMemorySize, want);
+        (void)hipFuncSetAttribute((const void *)k_estep_stats<32>, hipFuncAttributeMaxDynamicSharedMemorySize, want);
+        (void)hipFuncSetAttribute((const void *)k_estep_stats<64>, hipFuncAttributeMaxDynamicSharedMemorySize, want);
+        (void)hipGetLastError();
+    }
+    done = true;
+    return hipSuccess;
 }
 
 hipError_t launch_estep_stats(const Shape &s, const Bufs &b, int init_mode, hipStream_t st)
