@@ -23,7 +23,7 @@ COMMON = [
 ]
 
 LIBS = {
-    "libcavi.so": ["cavi_kernels.hip", "cavi_api.cpp"],
+    "libcavi.so": ["cavi_kernels.hip", "estep_tiled.hip", "update.hip", "cavi_api.cpp"],
     "libcavi_synth.so": ["synth.hip"],
 }
 

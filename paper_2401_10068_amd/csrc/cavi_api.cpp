@@ -393,9 +393,13 @@ cavi_status cavi_sweep(cavi_ctx *ctx, int32_t n, double *elbo_host)
                                   ctx->stream));
         HIPCHK(hipMemcpyAsync(ctx->hctl, ctx->b.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
-        if (ctx->hctl->numeric)
+        if (ctx->hctl->numeric) {
+            // the rejected update wrote coefficients; rebuild them from the kept state
+            HIPCHK(launch_coef(ctx->s, ctx->b, ctx->stream));
+            HIPCHK(hipStreamSynchronize(ctx->stream));
             return fail(CAVI_E_NUMERIC, "sweep %d produced a non-finite value; state kept at sweep %d",
                         done + ctx->hctl->call_sweeps + 1, done + ctx->hctl->call_sweeps);
+        }
         done += seg;
     }
     return CAVI_OK;
@@ -425,9 +429,12 @@ cavi_status cavi_run(cavi_ctx *ctx, int32_t max_sweeps, double rel_tol, int32_t 
     const Ctl &h = *ctx->hctl;
     if (sweeps) *sweeps = h.call_sweeps;
     if (elbo) *elbo = h.elbo;
-    if (h.numeric)
+    if (h.numeric) {
+        HIPCHK(launch_coef(ctx->s, ctx->b, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
         return fail(CAVI_E_NUMERIC, "sweep %d produced a non-finite value; state kept at sweep %d",
                     h.call_sweeps + 1, h.call_sweeps);
+    }
     if (!h.converged) return fail(CAVI_E_NOTCONV, "not converged after %d sweeps", h.call_sweeps);
     return CAVI_OK;
 }

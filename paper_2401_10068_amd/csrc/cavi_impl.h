@@ -70,6 +70,14 @@ struct Shape {
     int32_t nblk;       // ceil(N / kBlock)
 };
 
+__device__ __forceinline__ bool sweep_skipped(const Ctl *c)
+{
+    return c->numeric || c->call_sweeps >= c->max_call || (c->stop_on_conv && c->converged);
+}
+
+// Bytes of LDS per block the device allows (set by prepare_kernels()).
+extern int g_lds_limit;
+
 size_t workspace_bytes(const Shape &s);
 void carve(const Shape &s, void *ws, Bufs &b);
 int choose_tile_rows(int G, int kt);
@@ -80,6 +88,9 @@ hipError_t prepare_kernels();
 
 // Launchers (enqueue only; return hipError_t of the launch).
 hipError_t launch_estep_stats(const Shape &s, const Bufs &b, int init_mode, hipStream_t st);
+// Tiled E-step kernel (estep_tiled.hip) for G in {16,32,48,64,96,128} and small K.
+bool tiled_supported(int K, int G);
+hipError_t launch_estep_tiled(const Shape &s, const Bufs &b, hipStream_t st);
 hipError_t launch_reduce(const Shape &s, const Bufs &b, int init_mode, hipStream_t st);
 hipError_t launch_mstep(const Shape &s, const Bufs &b, const Prior &p, int init_mode, hipStream_t st);
 hipError_t launch_coef(const Shape &s, const Bufs &b, hipStream_t st);

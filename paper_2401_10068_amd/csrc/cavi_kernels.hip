@@ -13,21 +13,12 @@
 #include <math.h>
 
 #include "cavi_impl.h"
-#include "devmath.h"
 
 namespace cavi {
 
 namespace {
 
-constexpr double kLn2Pi = 1.8378770664093454835606594728112;
-constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr int kMaxItems = kMaxKG / kBlock;  // (k, g) items per thread
-int g_lds_limit = 0;                         // bytes of LDS per block the device allows
-
-__device__ __forceinline__ bool sweep_skipped(const Ctl *c)
-{
-    return c->numeric || c->call_sweeps >= c->max_call || (c->stop_on_conv && c->converged);
-}
 
 // Squared distance in FP64 with separate multiply and add (no contraction),
 // so that the host reproduces it bit for bit.
@@ -209,193 +200,6 @@ __global__ __launch_bounds__(kBlock) void k_estep_stats(Shape s, const float *__
         }
         if (tid == 0) out[K + 2 * KG] = red[0];
         __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------------------------
-// totals[i] = sum over chunks of partials[chunk][i], in a fixed order: each of
-// the 4 waves sums a contiguous quarter of the chunks with 4 interleaved
-// accumulators, then the quarters are added in order.
-__global__ __launch_bounds__(kBlock) void k_reduce(const double *__restrict__ partials, int nchunk, int S,
-                                                   double *__restrict__ totals, const Ctl *__restrict__ ctl,
-                                                   int init_mode)
-{
-    if (!init_mode && sweep_skipped(ctl)) return;
-    __shared__ double part[4][64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int i = blockIdx.x * 64 + lane;
-    double acc = 0.0;
-    if (i < S) {
-        const int c0 = (int)(((int64_t)nchunk * w) / 4), c1 = (int)(((int64_t)nchunk * (w + 1)) / 4);
-        double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
-        int c = c0;
-        for (; c + 4 <= c1; c += 4) {
-            q0 += partials[(size_t)c * S + i];
-            q1 += partials[(size_t)(c + 1) * S + i];
-            q2 += partials[(size_t)(c + 2) * S + i];
-            q3 += partials[(size_t)(c + 3) * S + i];
-        }
-        for (; c < c1; ++c) q0 += partials[(size_t)c * S + i];
-        acc = (q0 + q1) + (q2 + q3);
-    }
-    part[w][lane] = acc;
-    __syncthreads();
-    if (w == 0 && i < S) totals[i] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
-}
-
-// ---------------------------------------------------------------------------------------------
-// FP32 coefficients of the E-step from the committed state:
-//   l_nk = c_k - sum_g (h_kg x_ng + q_kg)^2,  h = sqrt(E[tau]/2),  q = -m h,
-//   c_k = E ln pi_k + 1/2 sum_g (E ln tau_kg - ln 2pi - 1/beta_kg),
-// with E ln pi = psi(alpha_k) - psi(sum alpha), E[tau] = a/b, E ln tau = psi(a) - ln b.
-__device__ void write_coef(const Shape &s, const Bufs &b, double *sh_psum)
-{
-    const int G = s.G, K = s.K, KG = K * G, tid = threadIdx.x;
-    for (int q = tid; q < KG; q += kBlock) {
-        const double aa = b.a[q], bb = b.b[q], mm = b.m[q], bt = b.beta[q];
-        const double elt = dev_digamma(aa) - log(bb);
-        b.tmp[q] = 0.5 * (elt - kLn2Pi - 1.0 / bt);
-        const float hf = (float)sqrt(0.5 * aa / bb);
-        b.hq[2 * q] = hf;
-        b.hq[2 * q + 1] = (float)(-mm * (double)hf);
-        b.mf[q] = (float)mm;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double asum = 0.0;
-        for (int k = 0; k < K; ++k) asum += b.alpha[k];
-        *sh_psum = dev_digamma(asum);
-    }
-    __syncthreads();
-    if (tid < K) {
-        double c = dev_digamma(b.alpha[tid]) - *sh_psum;
-        for (int g = 0; g < G; ++g) c += b.tmp[tid * G + g];
-        b.cc[tid] = (float)c;
-    }
-    __syncthreads();
-}
-
-__global__ __launch_bounds__(kBlock) void k_coef(Shape s, Bufs b)
-{
-    __shared__ double psum;
-    write_coef(s, b, &psum);
-}
-
-// ---------------------------------------------------------------------------------------------
-// Conjugate updates from the totals, written with sums around the E-step's
-// FP32 centre c = mf:  T1 = sum r (x - c),  T2 = sum r (x - c)^2,
-//   alpha = alpha0 + N_k;  beta = beta0 + N_k;  m = c + (beta0 (m0 - c) + T1) / beta;
-//   a = a0 + N_k / 2;  b = b0 + 1/2 [T2 + beta0 (m0 - c)^2 - beta (m - c)^2],
-// then the lower bound at the new q(pi), q(mu, tau) and the row entropy H.
-// A non-finite value leaves the state untouched and raises ctl->numeric.
-__global__ __launch_bounds__(kBlock) void k_mstep(Shape s, Bufs b, Prior p, int init_mode)
-{
-    Ctl *ctl = b.ctl;
-    if (!init_mode && sweep_skipped(ctl)) return;
-    __shared__ double red[kBlock];
-    __shared__ double sh_asum, sh_psum, sh_lga0;
-    __shared__ int bad;
-    const int G = s.G, K = s.K, KG = K * G, tid = threadIdx.x;
-    const double *T0 = b.totals, *T1 = T0 + K, *T2 = T1 + KG;
-    const double H = T2[KG];
-    if (tid == 0) {
-        bad = 0;
-        sh_lga0 = dev_lgamma(p.a0);
-    }
-    if (tid < K) b.nalpha[tid] = p.alpha0 + T0[tid];
-    __syncthreads();
-    if (tid == 0) {
-        double asum = 0.0;
-        for (int k = 0; k < K; ++k) asum += b.nalpha[k];
-        sh_asum = asum;
-        sh_psum = dev_digamma(asum);
-    }
-    __syncthreads();
-
-    double acc = 0.0;
-    int mybad = 0;
-    const double half_ln_b0 = 0.5 * log(p.beta0 / kTwoPi);
-    const double a0lnb0 = p.a0 * log(p.b0);
-    for (int q = tid; q < KG; q += kBlock) {
-        const int k = q / G, g = q - k * G;
-        const double Nk = T0[k];
-        const double c = (double)b.mf[q];
-        const double m0p = b.m0[g] - c;
-        const double bt = p.beta0 + Nk;
-        const double mp = (p.beta0 * m0p + T1[q]) / bt;
-        const double mm = c + mp;
-        const double aa = p.a0 + 0.5 * Nk;
-        double bb = p.b0 + 0.5 * (T2[q] + p.beta0 * m0p * m0p - bt * mp * mp);
-        if (bb < p.b0) bb = p.b0;
-        b.nm[q] = mm;
-        b.nbeta[q] = bt;
-        b.na[q] = aa;
-        b.nb[q] = bb;
-        const double elt = dev_digamma(aa) - log(bb);
-        const double tb = aa / bb;
-        if (!init_mode) {
-            double sq = T2[q] - 2.0 * mp * T1[q] + Nk * mp * mp;  // sum r (x - m)^2
-            if (sq < 0.0) sq = 0.0;
-            const double dm0 = mp - m0p;                        // m - m0
-            acc += 0.5 * (Nk * (elt - kLn2Pi) - tb * sq - Nk / bt);
-            acc += half_ln_b0 + 0.5 * elt - 0.5 * p.beta0 * (tb * dm0 * dm0 + 1.0 / bt) + a0lnb0 - sh_lga0
-                   + (p.a0 - 1.0) * elt - p.b0 * tb;
-            acc -= 0.5 * log(bt / kTwoPi) + 0.5 * elt - 0.5 + aa * log(bb) - dev_lgamma(aa) + (aa - 1.0) * elt - aa;
-        }
-        if (!isfinite(mm) || !isfinite(bb) || !isfinite(elt) || !isfinite(T2[q])) mybad = 1;
-    }
-    if (mybad) atomicOr(&bad, 1);
-    red[tid] = acc;
-    __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
-        if (tid < off) red[tid] += red[tid + off];
-        __syncthreads();
-    }
-    __shared__ double sh_L;
-    if (tid == 0) {
-        double L = red[0] + H;
-        const double asum = sh_asum;
-        L += dev_lgamma(K * p.alpha0) - K * dev_lgamma(p.alpha0) - dev_lgamma(asum);
-        for (int k = 0; k < K; ++k) {
-            const double ak = b.nalpha[k];
-            const double elnpi = dev_digamma(ak) - sh_psum;
-            L += T0[k] * elnpi + (p.alpha0 - 1.0) * elnpi + dev_lgamma(ak) - (ak - 1.0) * elnpi;
-            if (!isfinite(ak)) bad = 1;
-        }
-        if (!init_mode && !isfinite(L)) bad = 1;
-        sh_L = L;
-    }
-    __syncthreads();
-    if (bad) {
-        if (tid == 0) ctl->numeric = 1;
-        return;
-    }
-    if (tid < K) b.alpha[tid] = b.nalpha[tid];
-    for (int q = tid; q < KG; q += kBlock) {
-        b.m[q] = b.nm[q];
-        b.beta[q] = b.nbeta[q];
-        b.a[q] = b.na[q];
-        b.b[q] = b.nb[q];
-    }
-    __syncthreads();
-    write_coef(s, b, &sh_psum);
-    if (tid == 0) {
-        if (init_mode) {
-            ctl->sweeps = 0;
-            ctl->call_sweeps = 0;
-            ctl->converged = 0;
-            ctl->numeric = 0;
-            ctl->elbo = 0.0;
-        } else {
-            const double L = sh_L;
-            const int t = ctl->call_sweeps + 1;
-            if (t >= 2 && fabs(L - ctl->elbo) <= ctl->tol * fabs(L)) ctl->converged = 1;
-            ctl->elbo_prev = ctl->elbo;
-            ctl->elbo = L;
-            b.hist[(t - 1) % kHist] = L;
-            ctl->call_sweeps = t;
-            ctl->sweeps += 1;
-        }
     }
 }
 
@@ -615,8 +419,11 @@ hipError_t prepare_kernels()
     return hipSuccess;
 }
 
+int g_lds_limit = 0;
+
 hipError_t launch_estep_stats(const Shape &s, const Bufs &b, int init_mode, hipStream_t st)
 {
+    if (!init_mode && tiled_supported(s.K, s.G)) return launch_estep_tiled(s, b, st);
     switch (s.kt) {
     case 4: return launch_estep_t<4>(s, b, init_mode, st);
     case 8: return launch_estep_t<8>(s, b, init_mode, st);
@@ -626,24 +433,8 @@ hipError_t launch_estep_stats(const Shape &s, const Bufs &b, int init_mode, hipS
     }
 }
 
-hipError_t launch_reduce(const Shape &s, const Bufs &b, int init_mode, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_reduce, dim3((s.S + 63) / 64), dim3(kBlock), 0, st, b.partials, s.nchunk, s.S, b.totals,
-                       b.ctl, init_mode);
-    return hipGetLastError();
-}
 
-hipError_t launch_mstep(const Shape &s, const Bufs &b, const Prior &p, int init_mode, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_mstep, dim3(1), dim3(kBlock), 0, st, s, b, p, init_mode);
-    return hipGetLastError();
-}
 
-hipError_t launch_coef(const Shape &s, const Bufs &b, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_coef, dim3(1), dim3(kBlock), 0, st, s, b);
-    return hipGetLastError();
-}
 
 hipError_t launch_prior_mean(const Shape &s, const Bufs &b, hipStream_t st)
 {

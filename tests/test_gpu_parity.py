@@ -104,6 +104,11 @@ def test_one_sweep_small_workload(torch_cuda):
     (2100, 64, 64),
     (2049, 8, 512),
     (600, 2, 130),
+    (2 * 2048 + 300, 5, 48),
+    (3000, 13, 64),
+    (2048 + 128, 2, 128),
+    (2048 + 127, 7, 32),
+    (129, 4, 16),
 ])
 def test_one_sweep_ragged_overlapping(torch_cuda, N, K, G):
     X = overlapping(100 + K + G, N, K, G)
