@@ -1,21 +1,32 @@
-// Tiled E-step + statistics kernel for the common shapes (G a multiple of 4
-// up to 128, K up to 16): the same arithmetic as k_estep_stats, organised for
-// gfx950.
+// Tiled, screened E-step + statistics kernel for the common shapes (G in
+// {16, 32, 48, 64, 96, 128}, K <= 16).  Same arithmetic as k_estep_stats
+// (row log-likelihood l_nk = c_k - sum_g (h_kg x_ng + q_kg)^2, log-sum-exp,
+// responsibilities below exp(-87) of the normaliser set to zero, statistics
+// around the FP32 centre m_kg), organised for gfx950 and for the sparsity of
+// the responsibilities.
 //
 // Per 2048-row chunk (the unit of the deterministic reduction), 128-row tiles
 // are staged in LDS (row stride G+4 floats; the next tile is prefetched into
 // registers while the current one is processed).  Per tile:
-//   1. E-step.  Wave w owns subpopulations k = w, w+4, ...; each lane owns
-//      two rows.  The coefficients of k are wave-uniform, so they arrive by
-//      scalar loads: l_nk = c_k - sum_g (h_kg x_ng + q_kg)^2.
-//   2. Log-sum-exp.  One thread per row: L_n, r_nk = exp(l_nk - L_n) (zero
-//      below exp(-87)), the entropy term, and a bitmask of the nonzero r_nk.
-//   3. Statistics.  Wave w walks rows 32w..32w+31, lanes over genes; for each
-//      subpopulation in the row's mask (a uniform scalar branch):
-//      T0 += r,  T1 += r d,  T2 += r d^2  with d = x - m_kg (FP32 centre).
-// Each wave sums its 512 rows of a chunk in FP32 (the sums are taken around
-// the previous mean, so they do not cancel); the four wave sums are promoted
-// to FP64 and added in wave order; the chunk partial is T0 | T1 | T2 | H.
+//   A. Screen.  Wave w owns subpopulations w, w+4, ...; each lane owns two
+//      rows; over the first GB = min(G, 16) genes it forms the partial sums
+//      P_nk.  Every term is non-negative, so U_nk = c_k - P_nk bounds l_nk
+//      from above (also in FP32: adding non-negative terms never lowers a
+//      rounded sum).  Coefficients are wave-uniform: scalar loads.
+//   B. Exact terms.  Wave w owns rows 32w..32w+31, two lanes per row (each
+//      sums half of the remaining genes with per-lane coefficients read from
+//      an LDS table).  First the subpopulation with the largest bound, then
+//      every k whose bound is within 87 of that exact value.  A k outside
+//      that set has l_nk - L_n < -87, so its responsibility is zero exactly
+//      as in the dense computation.  Then log-sum-exp over the computed set:
+//      responsibilities, entropy, counts, and a bitmask of nonzero r_nk.
+//   C. Statistics.  The same wave walks its rows with lanes over genes; a
+//      row with one responsibility of exactly 1 (the common case) adds d and
+//      d^2 to its subpopulation's sums, other rows add r d and r d^2 for each
+//      nonzero r (d = x - m_kg).
+// Each wave sums its rows of a chunk in FP32 (around the previous mean, so
+// without cancellation); the four wave sums are promoted to FP64 and added in
+// wave order; the chunk partial is written as T0 | T1 | T2 | H.
 #include <math.h>
 
 #include "cavi_impl.h"
@@ -24,19 +35,23 @@ namespace cavi {
 
 namespace {
 
-constexpr int kT = 128;        // rows per tile
+constexpr int kT = 128;  // rows per tile
+constexpr uint32_t kOneHot = 1u << 31;
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 template <int KT, int G>
 struct Cfg {
     static constexpr int XS = G + 4;                     // LDS row stride of the x tile
-    static constexpr int LS = (KT == 4) ? 12 : KT + 4;   // LDS row stride of l / r
-    static constexpr int KQ = KT / 4;                    // subpopulations per wave (E-step)
+    static constexpr int LS = (KT == 4) ? 12 : KT + 4;   // LDS row stride of the partial / exact l
+    static constexpr int PS = 2 * G + 4;                 // LDS row stride of the (h, q) table
+    static constexpr int KQ = KT / 4;                    // subpopulations per wave (screen)
     static constexpr int GS = (G + 63) / 64;             // gene slots per lane (statistics)
-    static constexpr int LOADS = (kT * G / 4) / kBlock;  // float4 loads per thread per tile
-    static constexpr int LDS_BYTES = (kT * XS + kT * LS) * 4 + kT * 4;
-    static_assert(G % 4 == 0, "G must be a multiple of 4");
-    static_assert((kT * G / 4) % kBlock == 0, "tile must split evenly into float4 loads");
+    static constexpr int LOADS = (kT * G / 4) / kBlock;  // 16-byte loads per thread per tile
+    static constexpr int GB = G < 16 ? G : 16;           // screened genes
+    static constexpr int HG = (G - GB) / 2;              // remaining genes per half row
+    static constexpr int LDS_BYTES = (kT * XS + kT * LS + KT * PS + KT) * 4;
+    static_assert(G % 4 == 0 && HG % 4 == 0, "gene blocks of 4");
+    static_assert((kT * G / 4) % kBlock == 0, "tile must split evenly into 16-byte loads");
     static_assert((KT + 2 * KT * G) * 8 <= kT * XS * 4, "chunk combine must fit the x tile");
 };
 
@@ -67,6 +82,39 @@ __device__ __forceinline__ void store_tile(const f4 (&pre)[(kT * G / 4) / kBlock
     }
 }
 
+// sum over N genes from g0 of (h x + q)^2, x from an LDS row, (h, q) from an LDS table row
+template <int N>
+__device__ __forceinline__ float tail_sum(const float *xr, const float *pr, int g0)
+{
+    float s = 0.f;
+#pragma unroll
+    for (int g = 0; g < N; g += 4) {
+        const f4 xv = *(const f4 *)(xr + g0 + g);
+        const f4 p0 = *(const f4 *)(pr + 2 * (g0 + g));
+        const f4 p1 = *(const f4 *)(pr + 2 * (g0 + g) + 4);
+        float u;
+        u = fmaf(xv.x, p0.x, p0.y); s = fmaf(u, u, s);
+        u = fmaf(xv.y, p0.z, p0.w); s = fmaf(u, u, s);
+        u = fmaf(xv.z, p1.x, p1.y); s = fmaf(u, u, s);
+        u = fmaf(xv.w, p1.z, p1.w); s = fmaf(u, u, s);
+    }
+    return s;
+}
+
+// Workgroup barrier that waits only for this wave's LDS operations: the
+// prefetch of the next tile (global loads) stays in flight across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 }  // namespace
 
 template <int KT, int G>
@@ -78,18 +126,25 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, const float 
                                                            const Ctl *__restrict__ ctl)
 {
     using C = Cfg<KT, G>;
-    constexpr int XS = C::XS, LS = C::LS, KQ = C::KQ, GS = C::GS;
+    constexpr int XS = C::XS, LS = C::LS, PS = C::PS, KQ = C::KQ, GS = C::GS, GB = C::GB, HG = C::HG;
     if (sweep_skipped(ctl)) return;
     extern __shared__ __align__(16) float smem[];
-    float *xs = smem;
-    float *ls = xs + kT * XS;
-    uint32_t *msk = (uint32_t *)(ls + kT * LS);
+    float *xs = smem;                 // kT x XS   x tile
+    float *ls = xs + kT * XS;         // kT x LS   partial, then exact, row log-likelihood sums
+    float *pt = ls + kT * LS;         // KT x PS   (h, q) table
+    float *ccs = pt + KT * PS;        // KT        c_k
     __shared__ double red[kBlock];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int K = s.K, KG = K * G;
 
+    for (int i = tid; i < KT * G; i += kBlock) {
+        const int k = i / G, g = i - k * G;
+        pt[k * PS + 2 * g] = k < K ? hq[2 * i] : 0.f;
+        pt[k * PS + 2 * g + 1] = k < K ? hq[2 * i + 1] : 0.f;
+    }
+    if (tid < KT) ccs[tid] = tid < K ? cc[tid] : 0.f;
     float mfv[KT][GS];
 #pragma unroll
     for (int k = 0; k < KT; ++k)
@@ -99,6 +154,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, const float 
             mfv[k][sl] = (k < K && g < G) ? mf[k * G + g] : 0.f;
         }
 
+    const int jl = lane & 31, half = lane >> 5;
     for (int chunk = blockIdx.x; chunk < s.nchunk; chunk += gridDim.x) {
         const int64_t r0 = (int64_t)chunk * kChunkRows;
         const int nrc = (int)min((int64_t)kChunkRows, s.N - r0);
@@ -118,18 +174,18 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, const float 
         for (int t = 0; t < ntiles; ++t) {
             const int nr = min(kT, nrc - t * kT);
             store_tile<G>(pre, xs, nr, tid);
-            __syncthreads();
+            lds_barrier();
             if (t + 1 < ntiles) load_tile<G>(pre, x, r0 + (int64_t)(t + 1) * kT, min(kT, nrc - (t + 1) * kT), tid);
 
-            // 1. E-step: sums of squares for rows lane and lane+64, subpopulations w + 4i
+            // A. screen: partial sums over the first GB genes, rows lane and lane+64
             {
                 float acc0[KQ], acc1[KQ];
 #pragma unroll
                 for (int i = 0; i < KQ; ++i) acc0[i] = acc1[i] = 0.f;
                 const float *xa = xs + lane * XS;
                 const float *xb = xs + (lane + 64) * XS;
-#pragma unroll 4
-                for (int gb = 0; gb < G; gb += 4) {
+#pragma unroll
+                for (int gb = 0; gb < GB; gb += 4) {
                     const f4 va = *(const f4 *)(xa + gb);
                     const f4 vb = *(const f4 *)(xb + gb);
 #pragma unroll
@@ -160,91 +216,163 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, const float 
                     }
                 }
             }
-            __syncthreads();
+            lds_barrier();
 
-            // 2. log-sum-exp for the wave's own 32 rows (lane jj < 32 owns row 32w + jj):
-            //    responsibilities stay in registers, with a bitmask of the nonzero ones.
+            // B. exact terms for the candidate subpopulations of row j (lanes jl, jl+32)
             const int jbase = 32 * w;
             const int nj = max(0, min(32, nr - jbase));
+            const int j = jbase + jl;
+            const bool act = jl < nj;
+            float *lr = ls + j * LS;
+            const float *xr = xs + j * XS;
+            uint32_t done = 0;
+            if (GB == G) {
+                if (act && half == 0) {
+#pragma unroll
+                    for (int k = 0; k < KT; ++k)
+                        if (k < K) lr[k] = ccs[k] - lr[k];
+                }
+                done = (1u << K) - 1u;
+            } else {
+                float U[KT];
+                float best = -INFINITY;
+                int kh = 0;
+#pragma unroll
+                for (int k = 0; k < KT; ++k) {
+                    U[k] = (k < K && act) ? ccs[k] - lr[k] : -INFINITY;
+                    if (U[k] > best) {
+                        best = U[k];
+                        kh = k;
+                    }
+                }
+                // exact l for the best-bounded subpopulation
+                const float pkh = lr[kh];
+                const float sh = act ? tail_sum<HG>(xr, pt + kh * PS, GB + half * HG) : 0.f;
+                const float so = __shfl_xor(sh, 32, 64);
+                const float lkh = ccs[kh] - (pkh + (half == 0 ? sh + so : so + sh));
+                uint32_t cm = 0;
+#pragma unroll
+                for (int k = 0; k < KT; ++k)
+                    if (k < K && k != kh && U[k] - lkh >= -kLogRCut) cm |= 1u << k;
+                if (!act) cm = 0;
+                __builtin_amdgcn_wave_barrier();
+                if (act && half == 0) lr[kh] = lkh;
+                done = 1u << kh;
+                // remaining candidates, one per lane per round
+                while (__ballot(cm != 0)) {
+                    const bool mine = cm != 0;
+                    const int k = mine ? __builtin_ctz(cm) : 0;
+                    const float pk = lr[k];
+                    const float sk = mine ? tail_sum<HG>(xr, pt + k * PS, GB + half * HG) : 0.f;
+                    const float sko = __shfl_xor(sk, 32, 64);
+                    __builtin_amdgcn_wave_barrier();
+                    if (mine) {
+                        if (half == 0) lr[k] = ccs[k] - (pk + (sk + sko));
+                        done |= 1u << k;
+                        cm &= cm - 1u;
+                    }
+                }
+            }
+            if (!act) done = 0;
+            __builtin_amdgcn_wave_barrier();
+
+            // log-sum-exp over the computed set (lanes jl < 32 own the rows)
             float rv[KT];
             uint32_t mk = 0;
 #pragma unroll
             for (int k = 0; k < KT; ++k) rv[k] = 0.f;
-            if (lane < nj) {
-                const float *lr = ls + (jbase + lane) * LS;
+            if (act && half == 0) {
                 float l[KT];
 #pragma unroll
-                for (int k = 0; k < KT; ++k) l[k] = (k < K) ? cc[k] - lr[k] : -INFINITY;
+                for (int k = 0; k < KT; ++k) l[k] = (done & (1u << k)) ? lr[k] : -INFINITY;
                 float mx = l[0];
 #pragma unroll
                 for (int k = 1; k < KT; ++k) mx = fmaxf(mx, l[k]);
                 float se = 0.f;
 #pragma unroll
                 for (int k = 0; k < KT; ++k)
-                    if (k < K) se += __expf(l[k] - mx);
+                    if (done & (1u << k)) se += __expf(l[k] - mx);
                 const float L = mx + __logf(se);
                 float h = isfinite(L) ? 0.f : __int_as_float(0x7fc00000);
+                int nz = 0;
 #pragma unroll
                 for (int k = 0; k < KT; ++k) {
-                    if (k < K) {
+                    if (done & (1u << k)) {
                         const float dl = l[k] - L;
                         if (dl > -kLogRCut) {
                             rv[k] = __expf(dl);
                             h -= rv[k] * dl;
                         }
                     }
-                    if (rv[k] != 0.f) mk |= 1u << k;
+                    if (rv[k] != 0.f) {
+                        mk |= 1u << k;
+                        ++nz;
+                    }
+                    t0[k] += rv[k];
+                }
+                if (nz == 1) {
+                    float rone = 0.f;
+#pragma unroll
+                    for (int k = 0; k < KT; ++k) rone += rv[k];
+                    if (rone == 1.f) mk |= kOneHot;
                 }
                 hacc += (double)h;
             }
 
-            // 3. statistics over the same rows, lanes over genes; the row's mask and
-            //    responsibilities are read across lanes into scalar registers.
+            // C. statistics over the same rows, lanes over genes.  For each subpopulation
+            //    (a static loop, so the sums stay in registers) walk the rows whose
+            //    responsibility for it is nonzero; rows with a single responsibility of
+            //    exactly 1 skip the multiplication.
             if (nj > 0) {
-                float xv[GS];
+                const bool own = act && half == 0;
 #pragma unroll
-                for (int sl = 0; sl < GS; ++sl) {
-                    const int g = lane + 64 * sl;
-                    xv[sl] = (g < G) ? xs[jbase * XS + g] : 0.f;
-                }
-                for (int jj = 0; jj < nj; ++jj) {
-                    float xn[GS];
-                    const int jn = jbase + min(jj + 1, nj - 1);
+                for (int k = 0; k < KT; ++k) {
+                    if (k >= K) break;
+                    const bool nzk = own && (mk & (1u << k));
+                    uint64_t one = __ballot(nzk && (mk & kOneHot));
+                    uint64_t soft = __ballot(nzk && !(mk & kOneHot));
+                    while (one) {
+                        const int jj = __builtin_ctzll(one);
+                        one &= one - 1;
 #pragma unroll
-                    for (int sl = 0; sl < GS; ++sl) {
-                        const int g = lane + 64 * sl;
-                        xn[sl] = (g < G) ? xs[jn * XS + g] : 0.f;
-                    }
-                    const uint32_t m = (uint32_t)__builtin_amdgcn_readlane((int)mk, jj);
-#pragma unroll
-                    for (int k = 0; k < KT; ++k) {
-                        if (m & (1u << k)) {
-                            const float r = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rv[k]), jj));
-                            t0[k] += r;
-#pragma unroll
-                            for (int sl = 0; sl < GS; ++sl) {
-                                const float d = xv[sl] - mfv[k][sl];
-                                const float wv = r * d;
-                                t1[k][sl] += wv;
-                                t2[k][sl] = fmaf(wv, d, t2[k][sl]);
-                            }
+                        for (int sl = 0; sl < GS; ++sl) {
+                            const int g = lane + 64 * sl;
+                            const float xv = (g < G) ? xs[(jbase + jj) * XS + g] : 0.f;
+                            const float d = xv - mfv[k][sl];
+                            t1[k][sl] += d;
+                            t2[k][sl] = fmaf(d, d, t2[k][sl]);
                         }
                     }
+                    while (soft) {
+                        const int jj = __builtin_ctzll(soft);
+                        soft &= soft - 1;
+                        const float r = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rv[k]), jj));
 #pragma unroll
-                    for (int sl = 0; sl < GS; ++sl) xv[sl] = xn[sl];
+                        for (int sl = 0; sl < GS; ++sl) {
+                            const int g = lane + 64 * sl;
+                            const float xv = (g < G) ? xs[(jbase + jj) * XS + g] : 0.f;
+                            const float d = xv - mfv[k][sl];
+                            const float wv = r * d;
+                            t1[k][sl] += wv;
+                            t2[k][sl] = fmaf(wv, d, t2[k][sl]);
+                        }
+                    }
                 }
             }
-            __syncthreads();
+            lds_barrier();
         }
 
         // combine the four waves in wave order (FP64, in the LDS of the x tile)
         double *cb = (double *)smem;
+        double c0[KT];
+#pragma unroll
+        for (int k = 0; k < KT; ++k) c0[k] = wave_sum((double)t0[k]);
         for (int ww = 0; ww < 4; ++ww) {
             if (w == ww) {
 #pragma unroll
                 for (int k = 0; k < KT; ++k) {
                     if (k < K) {
-                        if (lane == 0) cb[k] = (ww == 0) ? (double)t0[k] : cb[k] + (double)t0[k];
+                        if (lane == 0) cb[k] = (ww == 0) ? c0[k] : cb[k] + c0[k];
 #pragma unroll
                         for (int sl = 0; sl < GS; ++sl) {
                             const int g = lane + 64 * sl;
@@ -257,18 +385,18 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, const float 
                     }
                 }
             }
-            __syncthreads();
+            lds_barrier();
         }
         red[tid] = hacc;
-        __syncthreads();
+        lds_barrier();
         for (int off = kBlock / 2; off > 0; off >>= 1) {
             if (tid < off) red[tid] += red[tid + off];
-            __syncthreads();
+            lds_barrier();
         }
         double *out = partials + (size_t)chunk * s.S;
         for (int i = tid; i < K + 2 * KG; i += kBlock) out[i] = cb[i];
         if (tid == 0) out[K + 2 * KG] = red[0];
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -297,6 +425,12 @@ hipError_t launch_g(const Shape &s, const Bufs &b, hipStream_t st)
     }
 }
 
+int lds_bytes(int kt, int G)
+{
+    const int ls = (kt == 4) ? 12 : kt + 4;
+    return (kT * (G + 4) + kT * ls + kt * (2 * G + 4) + kt) * 4 + kBlock * 8;
+}
+
 }  // namespace
 
 bool tiled_supported(int K, int G)
@@ -306,9 +440,7 @@ bool tiled_supported(int K, int G)
     const int kt = choose_kt(K);
     const int gs = (G + 63) / 64;
     if (kt > 16 || kt * gs > 16) return false;
-    const int ls = (kt == 4) ? 12 : kt + 4;
-    const int bytes = (kT * (G + 4) + kT * ls) * 4 + kT * 4 + kBlock * 8;
-    return bytes <= (g_lds_limit > 0 ? g_lds_limit : 65536);
+    return lds_bytes(kt, G) <= (g_lds_limit > 0 ? g_lds_limit : 65536);
 }
 
 hipError_t launch_estep_tiled(const Shape &s, const Bufs &b, hipStream_t st)
