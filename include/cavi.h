@@ -130,6 +130,53 @@ cavi_status cavi_profile_estep(cavi_ctx *ctx, int32_t reps, float *avg_ms);
 /* Free the handle (and the workspace if library-owned).  NULL is a no-op. */
 cavi_status cavi_destroy(cavi_ctx *ctx);
 
+/* ------------------------------------------------------------------------
+ * Batches: B independent datasets sharing G, swept together (one set of
+ * launches per sweep, each dataset with its own convergence test).  The same
+ * kernels and the same per-dataset reduction order as a single-dataset
+ * handle, so a dataset's results are bitwise those of a single handle over
+ * its rows.
+ *   - x_dev holds the rows of all datasets concatenated (dataset 0 first),
+ *     sum(N) x G FP32, device memory, caller-owned, 16-byte aligned.
+ *   - N and K are HOST arrays of B entries; each dataset obeys the
+ *     single-dataset limits.
+ *   - prior->m0, if given, is a HOST array of B x G centres; NULL selects
+ *     each dataset's per-gene mean.
+ *   - The bound history keeps only the last value per dataset.
+ * ------------------------------------------------------------------------ */
+typedef struct cavi_batch cavi_batch;
+
+cavi_status cavi_batch_workspace_bytes(int32_t B, const int64_t *N, const int32_t *K, int32_t G,
+                                       size_t *bytes);
+
+cavi_status cavi_batch_create(cavi_batch **out, int32_t B, const float *x_dev, const int64_t *N,
+                              const int32_t *K, int32_t G, const cavi_prior *prior, void *hip_stream,
+                              void *workspace_dev, size_t ws_bytes);
+
+/* Standard initialisation of every dataset on the device; dataset b uses the
+ * SplitMix64 state seed + b (the same seeds as cavi_init_standard(seed + b)
+ * on a single handle over its rows). */
+cavi_status cavi_batch_init_standard(cavi_batch *bt, uint64_t seed);
+
+/* State of dataset b (host arrays sized by its own K; layout as for
+ * cavi_set_state).  Coefficients are rebuilt at the next sweep or run. */
+cavi_status cavi_batch_set_state(cavi_batch *bt, int32_t b, const double *alpha, const double *m,
+                                 const double *beta, const double *a, const double *bb);
+cavi_status cavi_batch_get_state(cavi_batch *bt, int32_t b, double *alpha, double *m, double *beta,
+                                 double *a, double *bb);
+
+/* Exactly n sweeps of every dataset; synchronises the stream. */
+cavi_status cavi_batch_sweep(cavi_batch *bt, int32_t n);
+
+/* Sweep every dataset until its own relative-change test passes (t >= 2
+ * sweeps of this call) or max_sweeps.  sweeps / elbo: NULL or B entries;
+ * n_converged: NULL or the count of converged datasets.  CAVI_E_NOTCONV
+ * when at least one dataset did not converge (all states valid). */
+cavi_status cavi_batch_run(cavi_batch *bt, int32_t max_sweeps, double rel_tol, int32_t *sweeps,
+                           double *elbo, int32_t *n_converged);
+
+cavi_status cavi_batch_destroy(cavi_batch *bt);
+
 /* Thread-local text of the last error ("" if none). */
 const char *cavi_last_error(void);
 

@@ -56,6 +56,15 @@ def lib():
             "cavi_get_prior_mean": (st, [vp, dp]),
             "cavi_profile_estep": (st, [vp, C.c_int32, C.POINTER(C.c_float)]),
             "cavi_destroy": (st, [vp]),
+            "cavi_batch_workspace_bytes": (st, [C.c_int32, vp, vp, C.c_int32, C.POINTER(C.c_size_t)]),
+            "cavi_batch_create": (st, [C.POINTER(vp), C.c_int32, vp, vp, vp, C.c_int32, C.POINTER(cavi_prior), vp,
+                                       vp, C.c_size_t]),
+            "cavi_batch_init_standard": (st, [vp, C.c_uint64]),
+            "cavi_batch_set_state": (st, [vp, C.c_int32, dp, dp, dp, dp, dp]),
+            "cavi_batch_get_state": (st, [vp, C.c_int32, dp, dp, dp, dp, dp]),
+            "cavi_batch_sweep": (st, [vp, C.c_int32]),
+            "cavi_batch_run": (st, [vp, C.c_int32, C.c_double, vp, vp, C.POINTER(C.c_int32)]),
+            "cavi_batch_destroy": (st, [vp]),
             "cavi_last_error": (C.c_char_p, []),
             "cavi_version": (C.c_char_p, []),
         }
@@ -227,6 +236,82 @@ class Cavi:
     def close(self):
         if self.h:
             cavi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------------- batches
+def cavi_batch_workspace_bytes(N, K, G: int) -> int:
+    N = np.ascontiguousarray(N, dtype=np.int64)
+    K = np.ascontiguousarray(K, dtype=np.int32)
+    n = C.c_size_t(0)
+    _check(lib().cavi_batch_workspace_bytes(int(N.size), N.ctypes.data, K.ctypes.data, int(G), C.byref(n)))
+    return int(n.value)
+
+
+class CaviBatch:
+    """Owning wrapper of a batch handle over concatenated rows ``x`` (sum(N) x G)."""
+
+    def __init__(self, x, N, K, alpha0=1.0, beta0=1e-3, a0=0.5, b0=0.5, m0=None, stream=None):
+        import torch
+
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 and x.dim() == 2
+                and x.is_contiguous()):
+            raise ValueError("x must be a contiguous 2-D float32 tensor on the GPU")
+        self.x = x
+        self.N = np.ascontiguousarray(N, dtype=np.int64)
+        self.K = np.ascontiguousarray(K, dtype=np.int32)
+        self.B = int(self.N.size)
+        self.G = int(x.shape[1])
+        if int(self.N.sum()) != x.shape[0]:
+            raise ValueError("sum(N) must equal the number of rows of x")
+        self._m0 = None if m0 is None else np.ascontiguousarray(m0, dtype=np.float64).reshape(self.B, self.G)
+        self.prior = cavi_prior(float(alpha0), float(beta0), float(a0), float(b0),
+                                _dp(self._m0) if self._m0 is not None else None)
+        nbytes = cavi_batch_workspace_bytes(self.N, self.K, self.G)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+        h = C.c_void_p()
+        _check(lib().cavi_batch_create(C.byref(h), self.B, C.c_void_p(x.data_ptr()), self.N.ctypes.data,
+                                       self.K.ctypes.data, self.G, C.byref(self.prior), _stream_ptr(stream),
+                                       C.c_void_p(self.workspace.data_ptr()), nbytes))
+        self.h = h
+
+    def init_standard(self, seed: int = 0):
+        _check(lib().cavi_batch_init_standard(self.h, C.c_uint64(seed)))
+
+    def set_state(self, b: int, alpha, m, beta, a, bb):
+        arrs = [np.ascontiguousarray(v, dtype=np.float64) for v in (alpha, m, beta, a, bb)]
+        _check(lib().cavi_batch_set_state(self.h, int(b), *[_dp(v) for v in arrs]))
+
+    def get_state(self, b: int):
+        K = int(self.K[b])
+        alpha = np.zeros(K)
+        m, beta, a, bb = (np.zeros((K, self.G)) for _ in range(4))
+        _check(lib().cavi_batch_get_state(self.h, int(b), _dp(alpha), _dp(m), _dp(beta), _dp(a), _dp(bb)))
+        return alpha, m, beta, a, bb
+
+    def sweep(self, n: int):
+        _check(lib().cavi_batch_sweep(self.h, int(n)))
+
+    def run(self, max_sweeps: int = 10000, rel_tol: float = 1e-6):
+        """Returns ``(sweeps[B], elbo[B], n_converged)``."""
+        sw = np.zeros(self.B, dtype=np.int32)
+        el = np.zeros(self.B)
+        nc = C.c_int32(0)
+        st = lib().cavi_batch_run(self.h, int(max_sweeps), float(rel_tol), sw.ctypes.data, el.ctypes.data,
+                                  C.byref(nc))
+        if st != CAVI_E_NOTCONV:
+            _check(st)
+        return sw, el, int(nc.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(lib().cavi_batch_destroy(self.h))
             self.h = None
 
     def __del__(self):

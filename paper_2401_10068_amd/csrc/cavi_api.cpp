@@ -1,6 +1,8 @@
 // Host runtime behind include/cavi.h: argument checks, workspace, the
-// k-means++ initialisation driver, hipGraph-captured sweeps, and the
-// convergence loop.  All device work is in cavi_kernels.hip.
+// k-means++ initialisation drivers, hipGraph-captured sweeps and the
+// convergence loops.  A single-dataset handle and a batch handle share one
+// implementation (a single dataset is a batch of one).  All device work is in
+// the .hip files.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -8,6 +10,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -38,6 +41,7 @@ cavi_status fail(cavi_status st, const char *fmt, ...)
     } while (0)
 
 constexpr int kGraphSweeps = 16;  // sweeps per captured graph
+constexpr int kHistSingle = 4096; // bounds kept by a single-dataset handle
 
 // SplitMix64 (Steele, Lea and Flood 2014) and floor(u53 * n / 2^53).
 uint64_t splitmix64(uint64_t &s)
@@ -56,9 +60,7 @@ uint64_t scaled_draw(uint64_t &s, uint64_t n)
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
-}  // namespace
-
-struct cavi_ctx {
+struct Handle {
     Shape s{};
     Bufs b{};
     Prior p{};
@@ -66,156 +68,141 @@ struct cavi_ctx {
     bool own_stream = false;
     void *ws = nullptr;
     bool own_ws = false;
-    bool have_state = false;
+    std::vector<Ds> ds;
+    std::vector<char> have_state;
+    bool coef_dirty = false;
     hipGraphExec_t graph = nullptr;
-    Ctl *hctl = nullptr;  // pinned host mirror of the control block
+    Ctl *hctl = nullptr;        // pinned host mirror of the control blocks
+    int32_t *hcount = nullptr;  // pinned
 };
 
-extern "C" {
-
-const char *cavi_last_error(void) { return g_err.c_str(); }
-
-const char *cavi_version(void) { return "cavi-gfx950 0.1.0"; }
-
-cavi_status cavi_prior_default(cavi_prior *prior)
+cavi_status make_shape(int32_t B, const int64_t *N, const int32_t *K, int32_t G, int hist_cap, Shape &s,
+                       std::vector<Ds> *ds)
 {
-    if (!prior) return fail(CAVI_E_INVAL, "prior is NULL");
-    prior->alpha0 = 1.0;
-    prior->beta0 = 1e-3;
-    prior->a0 = 0.5;
-    prior->b0 = 0.5;
-    prior->m0 = nullptr;
-    return CAVI_OK;
-}
-
-static cavi_status make_shape(int64_t N, int32_t G, int32_t K, Shape &s)
-{
-    if (K < 1 || K > kMaxK) return fail(CAVI_E_INVAL, "K=%d outside [1, %d]", K, kMaxK);
+    if (B < 1) return fail(CAVI_E_INVAL, "B=%d < 1", B);
     if (G < 1 || G > kMaxG) return fail(CAVI_E_INVAL, "G=%d outside [1, %d]", G, kMaxG);
-    if ((int64_t)K * G > kMaxKG) return fail(CAVI_E_INVAL, "K*G=%lld exceeds %d", (long long)K * G, kMaxKG);
-    if (N < K) return fail(CAVI_E_INVAL, "N=%lld < K=%d", (long long)N, K);
-    if (N >= ((int64_t)1 << 31)) return fail(CAVI_E_INVAL, "N=%lld too large", (long long)N);
-    s.N = N;
+    int kmax = 0;
+    int64_t ntot = 0, nmax = 0, nchunk = 0;
+    for (int i = 0; i < B; ++i) {
+        if (K[i] < 1 || K[i] > kMaxK) return fail(CAVI_E_INVAL, "K=%d outside [1, %d] (dataset %d)", K[i], kMaxK, i);
+        if ((int64_t)K[i] * G > kMaxKG)
+            return fail(CAVI_E_INVAL, "K*G=%lld exceeds %d (dataset %d)", (long long)K[i] * G, kMaxKG, i);
+        if (N[i] < K[i]) return fail(CAVI_E_INVAL, "N=%lld < K=%d (dataset %d)", (long long)N[i], K[i], i);
+        if (N[i] >= ((int64_t)1 << 31)) return fail(CAVI_E_INVAL, "N=%lld too large (dataset %d)", (long long)N[i], i);
+        kmax = std::max(kmax, (int)K[i]);
+        if (ds) ds->push_back(Ds{ntot, (int32_t)N[i], K[i], (int32_t)nchunk, (int32_t)((N[i] + kChunkRows - 1) / kChunkRows)});
+        ntot += N[i];
+        nmax = std::max(nmax, N[i]);
+        nchunk += (N[i] + kChunkRows - 1) / kChunkRows;
+    }
+    if (nchunk >= ((int64_t)1 << 31)) return fail(CAVI_E_INVAL, "too many rows");
+    s.B = B;
     s.G = G;
-    s.K = K;
-    s.nchunk = (int32_t)((N + kChunkRows - 1) / kChunkRows);
-    s.S = K + 2 * K * G + 1;
-    s.kt = choose_kt(K);
+    s.Kmax = kmax;
+    s.kt = choose_kt(kmax);
+    s.Smax = kmax + 2 * kmax * G + 1;
+    s.nchunk = (int32_t)nchunk;
     s.tile_rows = choose_tile_rows(G, s.kt);
-    s.nblk = (int32_t)((N + kBlock - 1) / kBlock);
+    s.hist_cap = hist_cap;
+    s.Ntot = ntot;
+    s.Nmax = nmax;
     return CAVI_OK;
 }
 
-cavi_status cavi_workspace_bytes(int64_t N, int32_t G, int32_t K, size_t *bytes)
+void destroy_handle(Handle *h)
 {
-    if (!bytes) return fail(CAVI_E_INVAL, "bytes is NULL");
-    Shape s;
-    cavi_status st = make_shape(N, G, K, s);
-    if (st != CAVI_OK) return st;
-    *bytes = workspace_bytes(s);
-    return CAVI_OK;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    if (h->own_ws && h->ws) (void)hipFree(h->ws);
+    if (h->hctl) (void)hipHostFree(h->hctl);
+    if (h->hcount) (void)hipHostFree(h->hcount);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
 }
 
-cavi_status cavi_destroy(cavi_ctx *ctx)
+cavi_status check_prior(const cavi_prior *prior, Prior &p)
 {
-    if (!ctx) return CAVI_OK;
-    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
-    if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
-    if (ctx->hctl) (void)hipHostFree(ctx->hctl);
-    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
-    delete ctx;
-    return CAVI_OK;
-}
-
-cavi_status cavi_create(cavi_ctx **out, const float *x_dev, int64_t N, int32_t G, int32_t K,
-                        const cavi_prior *prior, void *hip_stream, void *workspace_dev, size_t ws_bytes)
-{
-    if (!out) return fail(CAVI_E_INVAL, "out is NULL");
-    *out = nullptr;
-    if (!x_dev) return fail(CAVI_E_INVAL, "x_dev is NULL");
-    if (((uintptr_t)x_dev) & 15) return fail(CAVI_E_INVAL, "x_dev is not 16-byte aligned");
-    Shape s;
-    cavi_status st = make_shape(N, G, K, s);
-    if (st != CAVI_OK) return st;
     cavi_prior pr;
     cavi_prior_default(&pr);
     if (prior) pr = *prior;
     if (!finite_pos(pr.alpha0) || !finite_pos(pr.beta0) || !finite_pos(pr.a0) || !finite_pos(pr.b0))
         return fail(CAVI_E_INVAL, "prior hyperparameters must be finite and > 0");
-    if (pr.m0)
-        for (int g = 0; g < G; ++g)
-            if (!isfinite(pr.m0[g])) return fail(CAVI_E_INVAL, "prior m0[%d] is not finite", g);
-    const size_t need = workspace_bytes(s);
+    p = Prior{pr.alpha0, pr.beta0, pr.a0, pr.b0};
+    return CAVI_OK;
+}
+
+// Shared create: validation done by the caller except for device resources.
+cavi_status create_handle(Handle *h, const float *x_dev, int32_t B, const int64_t *N, const int32_t *K, int32_t G,
+                          const cavi_prior *prior, const double *m0_host, int hist_cap, void *hip_stream,
+                          void *workspace_dev, size_t ws_bytes)
+{
+    if (!x_dev) return fail(CAVI_E_INVAL, "x_dev is NULL");
+    if (((uintptr_t)x_dev) & 15) return fail(CAVI_E_INVAL, "x_dev is not 16-byte aligned");
+    cavi_status st = make_shape(B, N, K, G, hist_cap, h->s, &h->ds);
+    if (st != CAVI_OK) return st;
+    st = check_prior(prior, h->p);
+    if (st != CAVI_OK) return st;
+    if (m0_host)
+        for (size_t i = 0; i < (size_t)B * G; ++i)
+            if (!isfinite(m0_host[i])) return fail(CAVI_E_INVAL, "prior m0[%zu] is not finite", i);
+    const size_t need = workspace_bytes(h->s);
     if (workspace_dev) {
         if (ws_bytes < need) return fail(CAVI_E_NOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, need);
         if (((uintptr_t)workspace_dev) & 255) return fail(CAVI_E_INVAL, "workspace is not 256-byte aligned");
     }
     hipError_t e = prepare_kernels();
     if (e != hipSuccess) return fail(CAVI_E_HIP, "device query: %s", hipGetErrorString(e));
-    s.tile_rows = choose_tile_rows(G, s.kt);
-    if (s.tile_rows < 16) return fail(CAVI_E_INVAL, "G=%d needs more LDS per block than the device has", G);
-    cavi_ctx *c = new cavi_ctx;
-    c->s = s;
-    c->p = Prior{pr.alpha0, pr.beta0, pr.a0, pr.b0};
+    h->s.tile_rows = choose_tile_rows(G, h->s.kt);
+    if (h->s.tile_rows < 16) return fail(CAVI_E_INVAL, "G=%d needs more LDS per block than the device has", G);
     if (hip_stream) {
-        c->stream = (hipStream_t)hip_stream;
+        h->stream = (hipStream_t)hip_stream;
     } else {
-        e = hipStreamCreate(&c->stream);
-        if (e != hipSuccess) {
-            delete c;
-            return fail(CAVI_E_HIP, "hipStreamCreate: %s", hipGetErrorString(e));
-        }
-        c->own_stream = true;
+        e = hipStreamCreate(&h->stream);
+        if (e != hipSuccess) return fail(CAVI_E_HIP, "hipStreamCreate: %s", hipGetErrorString(e));
+        h->own_stream = true;
     }
     if (workspace_dev) {
-        c->ws = workspace_dev;
+        h->ws = workspace_dev;
     } else {
-        e = hipMalloc(&c->ws, need);
+        e = hipMalloc(&h->ws, need);
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            cavi_destroy(c);
+            h->ws = nullptr;
             return fail(CAVI_E_NOMEM, "hipMalloc(%zu): %s", need, hipGetErrorString(e));
         }
-        c->own_ws = true;
+        h->own_ws = true;
     }
-    e = hipHostMalloc((void **)&c->hctl, sizeof(Ctl), hipHostMallocDefault);
-    if (e != hipSuccess) {
-        cavi_destroy(c);
-        return fail(CAVI_E_HIP, "hipHostMalloc: %s", hipGetErrorString(e));
-    }
-    carve(s, c->ws, c->b);
-    c->b.x = x_dev;
-    cavi_status rs = CAVI_OK;
-    if (pr.m0) {
-        e = hipMemcpyAsync(c->b.m0, pr.m0, sizeof(double) * G, hipMemcpyHostToDevice, c->stream);
-    } else {
-        e = launch_prior_mean(s, c->b, c->stream);
-    }
-    if (e == hipSuccess) e = launch_ctl_begin(c->b, 0, 0, 0.0, 1, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) {
-        rs = fail(CAVI_E_HIP, "create: %s", hipGetErrorString(e));
-        cavi_destroy(c);
-        return rs;
-    }
-    *out = c;
+    HIPCHK(hipHostMalloc((void **)&h->hctl, sizeof(Ctl) * B, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&h->hcount, sizeof(int32_t), hipHostMallocDefault));
+    carve(h->s, h->ws, h->b);
+    h->b.x = x_dev;
+    std::vector<int32_t> chunk_ds(h->s.nchunk);
+    for (int i = 0; i < B; ++i)
+        for (int c = 0; c < h->ds[i].nchunk; ++c) chunk_ds[h->ds[i].chunk0 + c] = i;
+    HIPCHK(hipMemcpyAsync((void *)h->b.ds, h->ds.data(), sizeof(Ds) * B, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync((void *)h->b.chunk_ds, chunk_ds.data(), sizeof(int32_t) * h->s.nchunk,
+                          hipMemcpyHostToDevice, h->stream));
+    if (m0_host)
+        HIPCHK(hipMemcpyAsync(h->b.m0, m0_host, sizeof(double) * B * G, hipMemcpyHostToDevice, h->stream));
+    else
+        HIPCHK(launch_prior_mean(h->s, h->b, h->stream));
+    HIPCHK(launch_ctl_begin(h->s, h->b, 0, 0, 0.0, 1, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->have_state.assign(B, 0);
     return CAVI_OK;
 }
 
-cavi_status cavi_get_prior_mean(cavi_ctx *ctx, double *m0_host)
+bool all_have_state(const Handle *h)
 {
-    if (!ctx || !m0_host) return fail(CAVI_E_INVAL, "NULL argument");
-    HIPCHK(hipMemcpyAsync(m0_host, ctx->b.m0, sizeof(double) * ctx->s.G, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    return CAVI_OK;
+    for (char c : h->have_state)
+        if (!c) return false;
+    return true;
 }
 
-cavi_status cavi_set_state(cavi_ctx *ctx, const double *alpha, const double *m, const double *beta,
-                           const double *a, const double *b)
+cavi_status set_state_one(Handle *h, int bi, const double *alpha, const double *m, const double *beta,
+                          const double *a, const double *b)
 {
-    if (!ctx || !alpha || !m || !beta || !a || !b) return fail(CAVI_E_INVAL, "NULL argument");
-    const int K = ctx->s.K, KG = K * ctx->s.G;
+    if (!alpha || !m || !beta || !a || !b) return fail(CAVI_E_INVAL, "NULL argument");
+    const int K = h->ds[bi].K, G = h->s.G, KG = K * G;
     for (int k = 0; k < K; ++k)
         if (!finite_pos(alpha[k])) return fail(CAVI_E_INVAL, "alpha[%d] must be finite and > 0", k);
     for (int i = 0; i < KG; ++i) {
@@ -223,82 +210,104 @@ cavi_status cavi_set_state(cavi_ctx *ctx, const double *alpha, const double *m, 
         if (!finite_pos(beta[i]) || !finite_pos(a[i]) || !finite_pos(b[i]))
             return fail(CAVI_E_INVAL, "beta/a/b[%d] must be finite and > 0", i);
     }
-    const Bufs &B = ctx->b;
-    HIPCHK(hipMemcpyAsync(B.alpha, alpha, sizeof(double) * K, hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(hipMemcpyAsync(B.m, m, sizeof(double) * KG, hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(hipMemcpyAsync(B.beta, beta, sizeof(double) * KG, hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(hipMemcpyAsync(B.a, a, sizeof(double) * KG, hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(hipMemcpyAsync(B.b, b, sizeof(double) * KG, hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(launch_coef(ctx->s, B, ctx->stream));
-    HIPCHK(launch_ctl_begin(B, 0, 0, 0.0, 1, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    ctx->have_state = true;
+    const size_t kb = (size_t)bi * h->s.Kmax, kg = kb * G;
+    const Bufs &B = h->b;
+    HIPCHK(hipMemcpyAsync(B.alpha + kb, alpha, sizeof(double) * K, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(B.m + kg, m, sizeof(double) * KG, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(B.beta + kg, beta, sizeof(double) * KG, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(B.a + kg, a, sizeof(double) * KG, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(B.b + kg, b, sizeof(double) * KG, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->have_state[bi] = 1;
+    h->coef_dirty = true;
     return CAVI_OK;
 }
 
-cavi_status cavi_get_state(cavi_ctx *ctx, double *alpha, double *m, double *beta, double *a, double *b)
+cavi_status refresh_coef(Handle *h)
 {
-    if (!ctx) return fail(CAVI_E_INVAL, "ctx is NULL");
-    if (!ctx->have_state) return fail(CAVI_E_STATE, "no state: call cavi_init_standard or cavi_set_state");
-    const int K = ctx->s.K, KG = K * ctx->s.G;
-    const Bufs &B = ctx->b;
-    if (alpha) HIPCHK(hipMemcpyAsync(alpha, B.alpha, sizeof(double) * K, hipMemcpyDeviceToHost, ctx->stream));
-    if (m) HIPCHK(hipMemcpyAsync(m, B.m, sizeof(double) * KG, hipMemcpyDeviceToHost, ctx->stream));
-    if (beta) HIPCHK(hipMemcpyAsync(beta, B.beta, sizeof(double) * KG, hipMemcpyDeviceToHost, ctx->stream));
-    if (a) HIPCHK(hipMemcpyAsync(a, B.a, sizeof(double) * KG, hipMemcpyDeviceToHost, ctx->stream));
-    if (b) HIPCHK(hipMemcpyAsync(b, B.b, sizeof(double) * KG, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (!h->coef_dirty) return CAVI_OK;
+    HIPCHK(launch_coef(h->s, h->b, h->stream));
+    HIPCHK(launch_ctl_begin(h->s, h->b, 0, 0, 0.0, 1, h->stream));
+    h->coef_dirty = false;
     return CAVI_OK;
 }
 
-// ---------------------------------------------------------------------------------------------
-// standard initialisation (k-means++ with integer D^2 weights)
-
-static cavi_status seed_row_to_device(cavi_ctx *c, int j, int64_t row)
+cavi_status get_state_one(Handle *h, int bi, double *alpha, double *m, double *beta, double *a, double *b)
 {
-    HIPCHK(hipMemcpyAsync(c->b.seeds + (size_t)j * c->s.G, c->b.x + (size_t)row * c->s.G, sizeof(float) * c->s.G,
-                          hipMemcpyDeviceToDevice, c->stream));
+    if (!h->have_state[bi]) return fail(CAVI_E_STATE, "no state: call init_standard or set_state");
+    const int K = h->ds[bi].K, KG = K * h->s.G;
+    const size_t kb = (size_t)bi * h->s.Kmax, kg = kb * h->s.G;
+    const Bufs &B = h->b;
+    if (alpha) HIPCHK(hipMemcpyAsync(alpha, B.alpha + kb, sizeof(double) * K, hipMemcpyDeviceToHost, h->stream));
+    if (m) HIPCHK(hipMemcpyAsync(m, B.m + kg, sizeof(double) * KG, hipMemcpyDeviceToHost, h->stream));
+    if (beta) HIPCHK(hipMemcpyAsync(beta, B.beta + kg, sizeof(double) * KG, hipMemcpyDeviceToHost, h->stream));
+    if (a) HIPCHK(hipMemcpyAsync(a, B.a + kg, sizeof(double) * KG, hipMemcpyDeviceToHost, h->stream));
+    if (b) HIPCHK(hipMemcpyAsync(b, B.b + kg, sizeof(double) * KG, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
     return CAVI_OK;
 }
 
-cavi_status cavi_init_standard(cavi_ctx *ctx, uint64_t seed)
+// statistics of the hard nearest-seed assignment, then one update, for every dataset
+cavi_status finish_init(Handle *h)
 {
-    if (!ctx) return fail(CAVI_E_INVAL, "ctx is NULL");
-    const Shape &s = ctx->s;
-    const Bufs &B = ctx->b;
-    hipStream_t st = ctx->stream;
+    const Shape &s = h->s;
+    const Bufs &B = h->b;
+    HIPCHK(hipMemcpyAsync(B.mf, B.seeds, sizeof(float) * s.B * s.Kmax * s.G, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(launch_estep_stats(s, B, 1, h->stream));
+    HIPCHK(launch_reduce(s, B, 1, h->stream));
+    HIPCHK(launch_mstep(s, B, h->p, 1, h->stream));
+    HIPCHK(hipMemcpyAsync(h->hctl, B.ctl, sizeof(Ctl) * s.B, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int i = 0; i < s.B; ++i)
+        if (h->hctl[i].numeric) return fail(CAVI_E_NUMERIC, "initial update of dataset %d is not finite", i);
+    std::fill(h->have_state.begin(), h->have_state.end(), 1);
+    h->coef_dirty = false;
+    return CAVI_OK;
+}
+
+// k-means++ seeds of dataset 0 driven from the host (many workgroups per pass)
+cavi_status init_single(Handle *h, uint64_t seed)
+{
+    const Shape &s = h->s;
+    const Bufs &B = h->b;
+    hipStream_t st = h->stream;
+    const int64_t N = h->ds[0].N;
+    const int nblk = (int)((N + kBlock - 1) / kBlock);
     uint64_t rng = seed;
     int clog2n = 0;
-    while (((int64_t)1 << clog2n) < s.N) ++clog2n;
-    std::vector<double> bmax(s.nblk), blockd(kBlock);
-    std::vector<unsigned long long> bsum(s.nblk);
-
-    int64_t row = (int64_t)scaled_draw(rng, (uint64_t)s.N);
-    cavi_status rs = seed_row_to_device(ctx, 0, row);
+    while (((int64_t)1 << clog2n) < N) ++clog2n;
+    std::vector<double> bmax(nblk), blockd(kBlock);
+    std::vector<unsigned long long> bsum(nblk);
+    auto put_seed = [&](int j, int64_t row) -> cavi_status {
+        HIPCHK(hipMemcpyAsync(B.seeds + (size_t)j * s.G, B.x + (size_t)row * s.G, sizeof(float) * s.G,
+                              hipMemcpyDeviceToDevice, st));
+        return CAVI_OK;
+    };
+    int64_t row = (int64_t)scaled_draw(rng, (uint64_t)N);
+    cavi_status rs = put_seed(0, row);
     if (rs != CAVI_OK) return rs;
-    HIPCHK(launch_d2(s, B, 0, 1, st));
-    for (int j = 1; j < s.K; ++j) {
-        HIPCHK(hipMemcpyAsync(bmax.data(), B.blockmax, sizeof(double) * s.nblk, hipMemcpyDeviceToHost, st));
+    HIPCHK(launch_d2(s, B, 0, 0, 1, st));
+    for (int j = 1; j < h->ds[0].K; ++j) {
+        HIPCHK(hipMemcpyAsync(bmax.data(), B.blockmax, sizeof(double) * nblk, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         double mx = 0.0;
-        for (int i = 0; i < s.nblk; ++i)
-            if (bmax[i] > mx) mx = bmax[i];
+        for (int i = 0; i < nblk; ++i) mx = std::max(mx, bmax[i]);
         if (mx == 0.0) {
-            row = (int64_t)scaled_draw(rng, (uint64_t)s.N);
+            row = (int64_t)scaled_draw(rng, (uint64_t)N);
         } else {
             int E;
             frexp(mx, &E);
             const int e = 62 - E - clog2n;
-            HIPCHK(launch_wsum(s, B, e, st));
-            HIPCHK(hipMemcpyAsync(bsum.data(), B.blocksum, sizeof(unsigned long long) * s.nblk,
-                                  hipMemcpyDeviceToHost, st));
+            HIPCHK(launch_wsum(s, B, 0, e, st));
+            HIPCHK(hipMemcpyAsync(bsum.data(), B.blocksum, sizeof(unsigned long long) * nblk, hipMemcpyDeviceToHost,
+                                  st));
             HIPCHK(hipStreamSynchronize(st));
             unsigned long long W = 0;
-            for (int i = 0; i < s.nblk; ++i) W += bsum[i];
+            for (int i = 0; i < nblk; ++i) W += bsum[i];
             const uint64_t t = scaled_draw(rng, W);
             unsigned long long cum = 0;
-            int blk = s.nblk - 1;
-            for (int i = 0; i < s.nblk; ++i) {
+            int blk = nblk - 1;
+            for (int i = 0; i < nblk; ++i) {
                 if (cum + bsum[i] > t) {
                     blk = i;
                     break;
@@ -306,7 +315,7 @@ cavi_status cavi_init_standard(cavi_ctx *ctx, uint64_t seed)
                 cum += bsum[i];
             }
             const int64_t base = (int64_t)blk * kBlock;
-            const int cnt = (int)std::min<int64_t>(kBlock, s.N - base);
+            const int cnt = (int)std::min<int64_t>(kBlock, N - base);
             HIPCHK(hipMemcpyAsync(blockd.data(), B.mind2 + base, sizeof(double) * cnt, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             row = base + cnt - 1;
@@ -318,26 +327,27 @@ cavi_status cavi_init_standard(cavi_ctx *ctx, uint64_t seed)
                 }
             }
         }
-        rs = seed_row_to_device(ctx, j, row);
+        rs = put_seed(j, row);
         if (rs != CAVI_OK) return rs;
-        HIPCHK(launch_d2(s, B, j, 0, st));
+        HIPCHK(launch_d2(s, B, 0, j, 0, st));
     }
-    // statistics of the hard assignment are taken around the seed rows
-    HIPCHK(hipMemcpyAsync(B.mf, B.seeds, sizeof(float) * s.K * s.G, hipMemcpyDeviceToDevice, st));
-    HIPCHK(launch_estep_stats(s, B, 1, st));
-    HIPCHK(launch_reduce(s, B, 1, st));
-    HIPCHK(launch_mstep(s, B, ctx->p, 1, st));
-    HIPCHK(hipMemcpyAsync(ctx->hctl, B.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (ctx->hctl->numeric) return fail(CAVI_E_NUMERIC, "initial update produced a non-finite value");
-    ctx->have_state = true;
-    return CAVI_OK;
+    return finish_init(h);
 }
 
-// ---------------------------------------------------------------------------------------------
-// sweeps
+// k-means++ of every dataset on the device; dataset b uses SplitMix64 state seed + b
+cavi_status init_batch(Handle *h, uint64_t seed)
+{
+    std::vector<unsigned long long> seeds(h->s.B);
+    for (int i = 0; i < h->s.B; ++i) seeds[i] = seed + (uint64_t)i;
+    // the totals array is free during initialisation: stage the seeds there
+    unsigned long long *dseeds = (unsigned long long *)h->b.totals;
+    HIPCHK(hipMemcpyAsync(dseeds, seeds.data(), sizeof(unsigned long long) * h->s.B, hipMemcpyHostToDevice,
+                          h->stream));
+    HIPCHK(launch_kmeanspp_batch(h->s, h->b, dseeds, h->stream));
+    return finish_init(h);
+}
 
-static cavi_status enqueue_sweeps(cavi_ctx *c, int n)
+cavi_status enqueue_sweeps(Handle *c, int n)
 {
     for (int i = 0; i < n; ++i) {
         HIPCHK(launch_estep_stats(c->s, c->b, 0, c->stream));
@@ -347,7 +357,7 @@ static cavi_status enqueue_sweeps(cavi_ctx *c, int n)
     return CAVI_OK;
 }
 
-static cavi_status ensure_graph(cavi_ctx *c)
+cavi_status ensure_graph(Handle *c)
 {
     if (c->graph) return CAVI_OK;
     hipGraph_t g = nullptr;
@@ -368,8 +378,8 @@ static cavi_status ensure_graph(cavi_ctx *c)
     return CAVI_OK;
 }
 
-// Enqueue enough captured sweeps to cover n (the kernels skip past the call's limit).
-static cavi_status replay(cavi_ctx *c, int n)
+// Enqueue enough captured sweeps to cover n (the kernels skip past each call's limit).
+cavi_status replay(Handle *c, int n)
 {
     cavi_status rs = ensure_graph(c);
     if (rs != CAVI_OK) return rs;
@@ -377,87 +387,212 @@ static cavi_status replay(cavi_ctx *c, int n)
     return CAVI_OK;
 }
 
-cavi_status cavi_sweep(cavi_ctx *ctx, int32_t n, double *elbo_host)
+cavi_status numeric_failure(Handle *h)
 {
-    if (!ctx) return fail(CAVI_E_INVAL, "ctx is NULL");
+    // the rejected update wrote coefficients; rebuild them from the kept state
+    HIPCHK(launch_coef(h->s, h->b, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int i = 0; i < h->s.B; ++i)
+        if (h->hctl[i].numeric)
+            return fail(CAVI_E_NUMERIC, "dataset %d: sweep %d produced a non-finite value; state kept at sweep %d", i,
+                        h->hctl[i].sweeps + 1, h->hctl[i].sweeps);
+    return fail(CAVI_E_NUMERIC, "non-finite value");
+}
+
+cavi_status sweep_n(Handle *h, int32_t n, double *elbo_host)
+{
     if (n < 0) return fail(CAVI_E_INVAL, "n=%d < 0", n);
-    if (!ctx->have_state) return fail(CAVI_E_STATE, "no state: call cavi_init_standard or cavi_set_state");
+    if (!all_have_state(h)) return fail(CAVI_E_STATE, "no state: call init_standard or set_state");
+    cavi_status rs = refresh_coef(h);
+    if (rs != CAVI_OK) return rs;
+    const int cap = h->s.hist_cap;
     int done = 0;
     while (done < n) {
-        const int seg = std::min(n - done, kHist);
-        HIPCHK(launch_ctl_begin(ctx->b, seg, 0, 0.0, 0, ctx->stream));
-        cavi_status rs = replay(ctx, seg);
+        const int seg = std::min(n - done, elbo_host ? cap : n - done);
+        HIPCHK(launch_ctl_begin(h->s, h->b, seg, 0, 0.0, 0, h->stream));
+        rs = replay(h, seg);
         if (rs != CAVI_OK) return rs;
         if (elbo_host)
-            HIPCHK(hipMemcpyAsync(elbo_host + done, ctx->b.hist, sizeof(double) * seg, hipMemcpyDeviceToHost,
-                                  ctx->stream));
-        HIPCHK(hipMemcpyAsync(ctx->hctl, ctx->b.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
-        HIPCHK(hipStreamSynchronize(ctx->stream));
-        if (ctx->hctl->numeric) {
-            // the rejected update wrote coefficients; rebuild them from the kept state
-            HIPCHK(launch_coef(ctx->s, ctx->b, ctx->stream));
-            HIPCHK(hipStreamSynchronize(ctx->stream));
-            return fail(CAVI_E_NUMERIC, "sweep %d produced a non-finite value; state kept at sweep %d",
-                        done + ctx->hctl->call_sweeps + 1, done + ctx->hctl->call_sweeps);
-        }
+            HIPCHK(hipMemcpyAsync(elbo_host + done, h->b.hist, sizeof(double) * seg, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(h->hctl, h->b.ctl, sizeof(Ctl) * h->s.B, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        for (int i = 0; i < h->s.B; ++i)
+            if (h->hctl[i].numeric) return numeric_failure(h);
         done += seg;
     }
     return CAVI_OK;
 }
 
-cavi_status cavi_run(cavi_ctx *ctx, int32_t max_sweeps, double rel_tol, int32_t *sweeps, double *elbo)
+// returns CAVI_OK when every dataset converged, CAVI_E_NOTCONV otherwise
+cavi_status run_all(Handle *h, int32_t max_sweeps, double rel_tol)
 {
-    if (!ctx) return fail(CAVI_E_INVAL, "ctx is NULL");
     if (max_sweeps < 1) return fail(CAVI_E_INVAL, "max_sweeps=%d < 1", max_sweeps);
     if (!(rel_tol >= 0.0) || !isfinite(rel_tol)) return fail(CAVI_E_INVAL, "rel_tol must be finite and >= 0");
-    if (!ctx->have_state) return fail(CAVI_E_STATE, "no state: call cavi_init_standard or cavi_set_state");
-    HIPCHK(launch_ctl_begin(ctx->b, max_sweeps, 1, rel_tol, 0, ctx->stream));
+    if (!all_have_state(h)) return fail(CAVI_E_STATE, "no state: call init_standard or set_state");
+    cavi_status rs = refresh_coef(h);
+    if (rs != CAVI_OK) return rs;
+    HIPCHK(launch_ctl_begin(h->s, h->b, max_sweeps, 1, rel_tol, 0, h->stream));
     int issued = 0;
-    int batch = 1;  // graphs between host checks, doubled up to 4
+    int batch = 1;  // graphs between host checks, doubled up to 8
     for (;;) {
         for (int i = 0; i < batch && issued < max_sweeps; ++i) {
-            cavi_status rs = replay(ctx, kGraphSweeps);
+            rs = replay(h, kGraphSweeps);
             if (rs != CAVI_OK) return rs;
             issued += kGraphSweeps;
         }
-        HIPCHK(hipMemcpyAsync(ctx->hctl, ctx->b.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
-        HIPCHK(hipStreamSynchronize(ctx->stream));
-        const Ctl &h = *ctx->hctl;
-        if (h.numeric || h.converged || h.call_sweeps >= max_sweeps || issued >= max_sweeps) break;
-        if (batch < 4) batch *= 2;
+        HIPCHK(launch_count_active(h->s, h->b, h->stream));
+        HIPCHK(hipMemcpyAsync(h->hcount, h->b.count, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (*h->hcount == 0 || issued >= max_sweeps) break;
+        if (batch < 8) batch *= 2;
     }
-    const Ctl &h = *ctx->hctl;
-    if (sweeps) *sweeps = h.call_sweeps;
-    if (elbo) *elbo = h.elbo;
-    if (h.numeric) {
-        HIPCHK(launch_coef(ctx->s, ctx->b, ctx->stream));
-        HIPCHK(hipStreamSynchronize(ctx->stream));
-        return fail(CAVI_E_NUMERIC, "sweep %d produced a non-finite value; state kept at sweep %d",
-                    h.call_sweeps + 1, h.call_sweeps);
+    HIPCHK(hipMemcpyAsync(h->hctl, h->b.ctl, sizeof(Ctl) * h->s.B, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    int notconv = 0;
+    for (int i = 0; i < h->s.B; ++i) {
+        if (h->hctl[i].numeric) return numeric_failure(h);
+        if (!h->hctl[i].converged) ++notconv;
     }
-    if (!h.converged) return fail(CAVI_E_NOTCONV, "not converged after %d sweeps", h.call_sweeps);
+    if (notconv) return fail(CAVI_E_NOTCONV, "%d dataset(s) not converged after %d sweeps", notconv, max_sweeps);
     return CAVI_OK;
+}
+
+}  // namespace
+
+struct cavi_ctx {
+    Handle h;
+};
+
+struct cavi_batch {
+    Handle h;
+};
+
+extern "C" {
+
+const char *cavi_last_error(void) { return g_err.c_str(); }
+
+const char *cavi_version(void) { return "cavi-gfx950 0.2.0"; }
+
+cavi_status cavi_prior_default(cavi_prior *prior)
+{
+    if (!prior) return fail(CAVI_E_INVAL, "prior is NULL");
+    prior->alpha0 = 1.0;
+    prior->beta0 = 1e-3;
+    prior->a0 = 0.5;
+    prior->b0 = 0.5;
+    prior->m0 = nullptr;
+    return CAVI_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// single dataset
+
+cavi_status cavi_workspace_bytes(int64_t N, int32_t G, int32_t K, size_t *bytes)
+{
+    if (!bytes) return fail(CAVI_E_INVAL, "bytes is NULL");
+    Shape s;
+    cavi_status st = make_shape(1, &N, &K, G, kHistSingle, s, nullptr);
+    if (st != CAVI_OK) return st;
+    *bytes = workspace_bytes(s);
+    return CAVI_OK;
+}
+
+cavi_status cavi_create(cavi_ctx **out, const float *x_dev, int64_t N, int32_t G, int32_t K,
+                        const cavi_prior *prior, void *hip_stream, void *workspace_dev, size_t ws_bytes)
+{
+    if (!out) return fail(CAVI_E_INVAL, "out is NULL");
+    *out = nullptr;
+    cavi_ctx *c = new cavi_ctx;
+    cavi_status st = create_handle(&c->h, x_dev, 1, &N, &K, G, prior, prior ? prior->m0 : nullptr, kHistSingle,
+                                   hip_stream, workspace_dev, ws_bytes);
+    if (st != CAVI_OK) {
+        destroy_handle(&c->h);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return CAVI_OK;
+}
+
+cavi_status cavi_destroy(cavi_ctx *ctx)
+{
+    if (!ctx) return CAVI_OK;
+    destroy_handle(&ctx->h);
+    delete ctx;
+    return CAVI_OK;
+}
+
+cavi_status cavi_get_prior_mean(cavi_ctx *ctx, double *m0_host)
+{
+    if (!ctx || !m0_host) return fail(CAVI_E_INVAL, "NULL argument");
+    HIPCHK(hipMemcpyAsync(m0_host, ctx->h.b.m0, sizeof(double) * ctx->h.s.G, hipMemcpyDeviceToHost, ctx->h.stream));
+    HIPCHK(hipStreamSynchronize(ctx->h.stream));
+    return CAVI_OK;
+}
+
+cavi_status cavi_init_standard(cavi_ctx *ctx, uint64_t seed)
+{
+    if (!ctx) return fail(CAVI_E_INVAL, "ctx is NULL");
+    return init_single(&ctx->h, seed);
+}
+
+cavi_status cavi_set_state(cavi_ctx *ctx, const double *alpha, const double *m, const double *beta,
+                           const double *a, const double *b)
+{
+    if (!ctx) return fail(CAVI_E_INVAL, "NULL argument");
+    cavi_status st = set_state_one(&ctx->h, 0, alpha, m, beta, a, b);
+    if (st != CAVI_OK) return st;
+    st = refresh_coef(&ctx->h);
+    if (st != CAVI_OK) return st;
+    HIPCHK(hipStreamSynchronize(ctx->h.stream));
+    return CAVI_OK;
+}
+
+cavi_status cavi_get_state(cavi_ctx *ctx, double *alpha, double *m, double *beta, double *a, double *b)
+{
+    if (!ctx) return fail(CAVI_E_INVAL, "ctx is NULL");
+    return get_state_one(&ctx->h, 0, alpha, m, beta, a, b);
+}
+
+cavi_status cavi_sweep(cavi_ctx *ctx, int32_t n, double *elbo_host)
+{
+    if (!ctx) return fail(CAVI_E_INVAL, "ctx is NULL");
+    return sweep_n(&ctx->h, n, elbo_host);
+}
+
+cavi_status cavi_run(cavi_ctx *ctx, int32_t max_sweeps, double rel_tol, int32_t *sweeps, double *elbo)
+{
+    if (!ctx) return fail(CAVI_E_INVAL, "ctx is NULL");
+    cavi_status st = run_all(&ctx->h, max_sweeps, rel_tol);
+    if (st == CAVI_OK || st == CAVI_E_NOTCONV) {
+        if (sweeps) *sweeps = ctx->h.hctl[0].call_sweeps;
+        if (elbo) *elbo = ctx->h.hctl[0].elbo;
+    }
+    return st;
 }
 
 cavi_status cavi_profile_estep(cavi_ctx *ctx, int32_t reps, float *avg_ms)
 {
     if (!ctx || !avg_ms) return fail(CAVI_E_INVAL, "NULL argument");
     if (reps < 1) return fail(CAVI_E_INVAL, "reps=%d < 1", reps);
-    if (!ctx->have_state) return fail(CAVI_E_STATE, "no state: call cavi_init_standard or cavi_set_state");
+    Handle *h = &ctx->h;
+    if (!all_have_state(h)) return fail(CAVI_E_STATE, "no state: call cavi_init_standard or cavi_set_state");
+    cavi_status rs = refresh_coef(h);
+    if (rs != CAVI_OK) return rs;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    HIPCHK(launch_ctl_begin(ctx->b, 1, 0, 0.0, 0, ctx->stream));
-    HIPCHK(hipEventRecord(e0, ctx->stream));
-    for (int i = 0; i < reps; ++i) HIPCHK(launch_estep_stats(ctx->s, ctx->b, 0, ctx->stream));
-    HIPCHK(hipEventRecord(e1, ctx->stream));
+    HIPCHK(launch_ctl_begin(h->s, h->b, 1, 0, 0.0, 0, h->stream));
+    HIPCHK(hipEventRecord(e0, h->stream));
+    for (int i = 0; i < reps; ++i) HIPCHK(launch_estep_stats(h->s, h->b, 0, h->stream));
+    HIPCHK(hipEventRecord(e1, h->stream));
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    HIPCHK(launch_ctl_begin(ctx->b, 0, 0, 0.0, 0, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(launch_ctl_begin(h->s, h->b, 0, 0, 0.0, 0, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
     *avg_ms = ms / (float)reps;
     return CAVI_OK;
 }
@@ -465,9 +600,97 @@ cavi_status cavi_profile_estep(cavi_ctx *ctx, int32_t reps, float *avg_ms)
 cavi_status cavi_get_responsibilities(cavi_ctx *ctx, float *r_dev)
 {
     if (!ctx || !r_dev) return fail(CAVI_E_INVAL, "NULL argument");
-    if (!ctx->have_state) return fail(CAVI_E_STATE, "no state: call cavi_init_standard or cavi_set_state");
-    HIPCHK(launch_resp(ctx->s, ctx->b, r_dev, ctx->stream));
+    if (!all_have_state(&ctx->h)) return fail(CAVI_E_STATE, "no state: call cavi_init_standard or cavi_set_state");
+    cavi_status rs = refresh_coef(&ctx->h);
+    if (rs != CAVI_OK) return rs;
+    HIPCHK(launch_resp(ctx->h.s, ctx->h.b, r_dev, ctx->h.stream));
     return CAVI_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// batches
+
+cavi_status cavi_batch_workspace_bytes(int32_t B, const int64_t *N, const int32_t *K, int32_t G, size_t *bytes)
+{
+    if (!bytes || !N || !K) return fail(CAVI_E_INVAL, "NULL argument");
+    Shape s;
+    cavi_status st = make_shape(B, N, K, G, 1, s, nullptr);
+    if (st != CAVI_OK) return st;
+    *bytes = workspace_bytes(s);
+    return CAVI_OK;
+}
+
+cavi_status cavi_batch_create(cavi_batch **out, int32_t B, const float *x_dev, const int64_t *N, const int32_t *K,
+                              int32_t G, const cavi_prior *prior, void *hip_stream, void *workspace_dev,
+                              size_t ws_bytes)
+{
+    if (!out) return fail(CAVI_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!N || !K) return fail(CAVI_E_INVAL, "N or K is NULL");
+    cavi_batch *c = new cavi_batch;
+    cavi_status st = create_handle(&c->h, x_dev, B, N, K, G, prior, prior ? prior->m0 : nullptr, 1, hip_stream,
+                                   workspace_dev, ws_bytes);
+    if (st != CAVI_OK) {
+        destroy_handle(&c->h);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return CAVI_OK;
+}
+
+cavi_status cavi_batch_destroy(cavi_batch *bt)
+{
+    if (!bt) return CAVI_OK;
+    destroy_handle(&bt->h);
+    delete bt;
+    return CAVI_OK;
+}
+
+cavi_status cavi_batch_init_standard(cavi_batch *bt, uint64_t seed)
+{
+    if (!bt) return fail(CAVI_E_INVAL, "batch is NULL");
+    return init_batch(&bt->h, seed);
+}
+
+cavi_status cavi_batch_set_state(cavi_batch *bt, int32_t b, const double *alpha, const double *m,
+                                 const double *beta, const double *a, const double *bb)
+{
+    if (!bt) return fail(CAVI_E_INVAL, "batch is NULL");
+    if (b < 0 || b >= bt->h.s.B) return fail(CAVI_E_INVAL, "dataset %d outside [0, %d)", b, bt->h.s.B);
+    return set_state_one(&bt->h, b, alpha, m, beta, a, bb);
+}
+
+cavi_status cavi_batch_get_state(cavi_batch *bt, int32_t b, double *alpha, double *m, double *beta, double *a,
+                                 double *bb)
+{
+    if (!bt) return fail(CAVI_E_INVAL, "batch is NULL");
+    if (b < 0 || b >= bt->h.s.B) return fail(CAVI_E_INVAL, "dataset %d outside [0, %d)", b, bt->h.s.B);
+    return get_state_one(&bt->h, b, alpha, m, beta, a, bb);
+}
+
+cavi_status cavi_batch_sweep(cavi_batch *bt, int32_t n)
+{
+    if (!bt) return fail(CAVI_E_INVAL, "batch is NULL");
+    return sweep_n(&bt->h, n, nullptr);
+}
+
+cavi_status cavi_batch_run(cavi_batch *bt, int32_t max_sweeps, double rel_tol, int32_t *sweeps, double *elbo,
+                           int32_t *n_converged)
+{
+    if (!bt) return fail(CAVI_E_INVAL, "batch is NULL");
+    Handle *h = &bt->h;
+    cavi_status st = run_all(h, max_sweeps, rel_tol);
+    if (st == CAVI_OK || st == CAVI_E_NOTCONV) {
+        int nc = 0;
+        for (int i = 0; i < h->s.B; ++i) {
+            if (sweeps) sweeps[i] = h->hctl[i].call_sweeps;
+            if (elbo) elbo[i] = h->hctl[i].elbo;
+            nc += h->hctl[i].converged ? 1 : 0;
+        }
+        if (n_converged) *n_converged = nc;
+    }
+    return st;
 }
 
 }  // extern "C"

@@ -1,5 +1,10 @@
 // Internal interface between the host runtime (cavi_api.cpp) and the gfx950
-// kernels (cavi_kernels.hip).  Not part of the public ABI.
+// kernels.  Not part of the public ABI.
+//
+// Every handle is a batch of B datasets that share G (a single-dataset
+// handle is a batch of one).  Rows of all datasets are concatenated in one
+// FP32 array; each dataset's rows are cut into 2048-row chunks numbered
+// globally.  Per-dataset arrays use a uniform stride of Kmax subpopulations.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,13 +19,11 @@ constexpr int kChunkRows = 2048;
 constexpr int kBlock = 256;
 // Responsibilities below exp(-kLogRCut) of the row's normaliser are zero.
 constexpr float kLogRCut = 87.0f;
-// Bound history capacity on the device.
-constexpr int kHist = 4096;
 constexpr int kMaxK = 64;
 constexpr int kMaxG = 512;
 constexpr int kMaxKG = 4096;
 
-// Control block in device memory (one per dataset).
+// Control block in device memory, one per dataset.
 struct Ctl {
     int32_t sweeps;        // sweeps since the state was set / initialised
     int32_t call_sweeps;   // sweeps of the current sweep/run call
@@ -38,36 +41,49 @@ struct Prior {
     double alpha0, beta0, a0, b0;
 };
 
-// Device buffers of one dataset (all carved from one workspace).
-struct Bufs {
-    const float *x;     // N x G data (caller-owned)
-    double *alpha;      // K      state q(pi)
-    double *m, *beta, *a, *b;  // K*G state q(mu, tau), k-major
-    double *nalpha, *nm, *nbeta, *na, *nb;  // next-state staging
-    double *m0;         // G prior centre
-    double *tmp;        // K*G scratch
-    float *cc;          // K   per-subpopulation constant of the row log-likelihood
-    float *hq;          // 2*K*G interleaved (h, q): u = h x + q, l = c - sum u^2
-    float *mf;          // K*G FP32 centre of the statistics (FP32 of m)
-    float *seeds;       // K*G seed rows (initialisation)
-    double *partials;   // nchunk * S per-chunk statistics
-    double *totals;     // S
-    double *hist;       // kHist bounds
-    Ctl *ctl;
-    double *mind2;      // N   (initialisation)
-    double *blockmax;   // nblk
-    unsigned long long *blocksum;  // nblk
-    double *colpart;    // nchunk * G (prior centre)
+// One dataset of a batch (device memory).
+struct Ds {
+    int64_t row0;     // first row in the concatenated data
+    int32_t N, K;     // rows, subpopulations
+    int32_t chunk0;   // first global chunk
+    int32_t nchunk;   // chunks of this dataset
 };
 
 struct Shape {
-    int64_t N;
-    int32_t G, K;
-    int32_t nchunk;     // ceil(N / kChunkRows)
-    int32_t S;          // K + 2 K G + 1 statistics per chunk
-    int32_t tile_rows;  // rows staged in LDS per tile
-    int32_t kt;         // compiled K bound (4, 8, 16, 32, 64)
-    int32_t nblk;       // ceil(N / kBlock)
+    int32_t B;          // datasets
+    int32_t G;          // genes (shared)
+    int32_t Kmax;       // stride of the per-dataset subpopulation arrays
+    int32_t kt;         // compiled K bound covering Kmax (4, 8, 16, 32, 64)
+    int32_t Smax;       // statistics per chunk: Kmax + 2 Kmax G + 1
+    int32_t nchunk;     // chunks of all datasets
+    int32_t tile_rows;  // rows per LDS tile of the generic kernel
+    int32_t hist_cap;   // bounds kept per dataset
+    int64_t Ntot;       // rows of all datasets
+    int64_t Nmax;       // rows of the largest dataset
+};
+
+// Device buffers (carved from one workspace, plus the caller's data).
+struct Bufs {
+    const float *x;       // Ntot x G data (caller-owned)
+    const Ds *ds;         // B
+    const int32_t *chunk_ds;  // nchunk: dataset of each global chunk
+    double *alpha;        // B x Kmax          q(pi)
+    double *m, *beta, *a, *b;  // B x Kmax x G  q(mu, tau)
+    double *nalpha, *nm, *nbeta, *na, *nb;  // next-state staging
+    double *m0;           // B x G prior centre
+    float *cc;            // B x Kmax         c_k of the row log-likelihood
+    float *hq;            // B x Kmax x G x 2  (h, q): u = h x + q, l = c - sum u^2
+    float *mf;            // B x Kmax x G     FP32 centre of the statistics
+    float *seeds;         // B x Kmax x G     seed rows (initialisation)
+    double *partials;     // nchunk x Smax    per-chunk statistics
+    double *totals;       // B x Smax
+    double *hist;         // B x hist_cap     bound after each sweep
+    Ctl *ctl;             // B
+    int32_t *count;       // 1: datasets still sweeping
+    double *mind2;        // Ntot             (initialisation)
+    double *blockmax;     // ceil(Nmax / 256)
+    unsigned long long *blocksum;  // ceil(Nmax / 256)
+    double *colpart;      // nchunk x G      (prior centre)
 };
 
 __device__ __forceinline__ bool sweep_skipped(const Ctl *c)
@@ -86,7 +102,8 @@ int choose_kt(int K);
 // Once per process, before the first launch: kernel attributes (dynamic LDS limit).
 hipError_t prepare_kernels();
 
-// Launchers (enqueue only; return hipError_t of the launch).
+// Launchers (enqueue only; return hipError_t of the launch).  init_mode: the
+// hard nearest-seed responsibilities of the standard initialisation.
 hipError_t launch_estep_stats(const Shape &s, const Bufs &b, int init_mode, hipStream_t st);
 // Tiled E-step kernel (estep_tiled.hip) for G in {16,32,48,64,96,128} and small K.
 bool tiled_supported(int K, int G);
@@ -95,10 +112,16 @@ hipError_t launch_reduce(const Shape &s, const Bufs &b, int init_mode, hipStream
 hipError_t launch_mstep(const Shape &s, const Bufs &b, const Prior &p, int init_mode, hipStream_t st);
 hipError_t launch_coef(const Shape &s, const Bufs &b, hipStream_t st);
 hipError_t launch_prior_mean(const Shape &s, const Bufs &b, hipStream_t st);
-hipError_t launch_d2(const Shape &s, const Bufs &b, int seed_index, int first, hipStream_t st);
-hipError_t launch_wsum(const Shape &s, const Bufs &b, int e, hipStream_t st);
 hipError_t launch_resp(const Shape &s, const Bufs &b, float *r, hipStream_t st);
-hipError_t launch_ctl_begin(const Bufs &b, int max_call, int stop_on_conv, double tol, int reset,
+hipError_t launch_ctl_begin(const Shape &s, const Bufs &b, int max_call, int stop_on_conv, double tol, int reset,
                             hipStream_t st);
+hipError_t launch_count_active(const Shape &s, const Bufs &b, hipStream_t st);
+// k-means++ of one dataset driven from the host (large N): running minimum
+// of the squared distances to the seeds and per-block sums of the weights.
+hipError_t launch_d2(const Shape &s, const Bufs &b, int dataset, int seed_index, int first, hipStream_t st);
+hipError_t launch_wsum(const Shape &s, const Bufs &b, int dataset, int e, hipStream_t st);
+// k-means++ of every dataset on the device, one workgroup per dataset.
+hipError_t launch_kmeanspp_batch(const Shape &s, const Bufs &b, const unsigned long long *seeds_dev,
+                                 hipStream_t st);
 
 }  // namespace cavi

@@ -1,15 +1,15 @@
-// gfx950 kernels of the mixture CAVI sweep.
+// gfx950 kernels of the mixture CAVI sweep: the generic E-step + statistics
+// kernel (any G, K up to 64; also the hard assignment of the standard
+// initialisation), prior centres, control blocks, responsibilities, and the
+// k-means++ seeding of the standard initialisation.
 //
 // One sweep (eq 12 applied to each factor of the mean-field family of eqs 9
-// and 13, Section 3.4) is three launches:
-//   k_estep_stats  expected log-likelihood of every row under every
-//                  subpopulation, log-sum-exp responsibilities, and per-chunk
-//                  sufficient statistics (weighted counts, sums and sums of
-//                  squares around the previous mean, entropy);
-//   k_reduce       fixed-order FP64 sum of the chunk partials;
-//   k_mstep        conjugate updates (forms of eqs 16, 17, 24), the lower
-//                  bound (eqs 10-11), the convergence test, and the FP32
-//                  coefficients of the next E-step (expectations of eqs 26-31).
+// and 13, Section 3.4) is three launches over all datasets of a handle:
+//   E-step + statistics  per 2048-row chunk (k_estep_stats here, or the tiled
+//                        kernel of estep_tiled.hip for the common shapes);
+//   k_reduce             fixed-order FP64 sum of each dataset's chunk partials;
+//   k_mstep              conjugate updates, lower bound, convergence test and
+//                        the next E-step's coefficients (update.hip).
 #include <math.h>
 
 #include "cavi_impl.h"
@@ -55,50 +55,80 @@ __device__ __forceinline__ void row_loglik(const float *xr, int G, int K, const 
         if (k < K) l[k] = cc[k] - l[k];
 }
 
+// SplitMix64 (Steele, Lea and Flood 2014) and floor(u53 * n / 2^53).
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long &s)
+{
+    unsigned long long z = (s += 0x9E3779B97F4A7C15ULL);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ unsigned long long scaled_draw(unsigned long long &s, unsigned long long n)
+{
+    const unsigned long long u = splitmix64(s) >> 11;
+    const unsigned long long hi = __umul64hi(u, n), lo = u * n;
+    return (hi << 11) | (lo >> 53);
+}
+
+// dataset owning a global row (binary search over the datasets' first rows)
+__device__ __forceinline__ int dataset_of_row(const Ds *ds, int B, int64_t row)
+{
+    int lo = 0, hi = B;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (ds[mid].row0 <= row) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------
-// E-step + statistics.  Grid-stride over 2048-row chunks; each chunk is staged
-// through LDS in tiles of tile_rows rows (row stride G+1 floats).  One thread
-// owns one row for the E-step; for the statistics one thread owns (k, g) items
-// and walks the tile's rows, skipping rows whose responsibility is exactly 0.
-// init_mode: responsibilities are the hard nearest-seed assignment instead.
+// Generic E-step + statistics.  Grid-stride over global chunks; each chunk is
+// staged through LDS in tiles of tile_rows rows (row stride G+1 floats).  One
+// thread owns one row for the E-step; for the statistics one thread owns
+// (k, g) items and walks the tile's rows, skipping rows whose responsibility
+// is exactly 0.  init_mode: responsibilities are the hard nearest-seed
+// assignment (ties to the lowest seed) instead.
 template <int KT>
-__global__ __launch_bounds__(kBlock) void k_estep_stats(Shape s, const float *__restrict__ x,
-                                                        const float *__restrict__ cc,
-                                                        const float2 *__restrict__ hq,
-                                                        const float *__restrict__ mf,
-                                                        const float *__restrict__ seeds,
-                                                        double *__restrict__ partials,
-                                                        const Ctl *__restrict__ ctl, int init_mode)
+__global__ __launch_bounds__(kBlock) void k_estep_stats(Shape s, Bufs bf, int init_mode)
 {
-    if (!init_mode && sweep_skipped(ctl)) return;
     extern __shared__ float smem[];
     __shared__ double red[kBlock];
-    const int G = s.G, K = s.K, KG = K * G;
+    const int G = s.G;
     const int TR = s.tile_rows, XS = G + 1, RS = KT + 1;
     float *xs = smem;
     float *rs = smem + TR * XS;
     const int tid = threadIdx.x;
-    const int nit = (KG + kBlock - 1) / kBlock;
-
-    float mfv[kMaxItems];
-#pragma unroll
-    for (int it = 0; it < kMaxItems; ++it) {
-        const int p = tid + it * kBlock;
-        mfv[it] = (it < nit && p < KG) ? mf[p] : 0.f;
-    }
 
     for (int chunk = blockIdx.x; chunk < s.nchunk; chunk += gridDim.x) {
+        const int bi = bf.chunk_ds[chunk];
+        const Ds d = bf.ds[bi];
+        if (!init_mode && sweep_skipped(bf.ctl + bi)) continue;
+        const int K = d.K, KG = K * G;
+        const int nit = (KG + kBlock - 1) / kBlock;
+        const size_t kb = (size_t)bi * s.Kmax;
+        const float *cc = bf.cc + kb;
+        const float2 *hq = (const float2 *)bf.hq + kb * G;
+        const float *mf = bf.mf + kb * G;
+        const float *seeds = bf.seeds + kb * G;
+        float mfv[kMaxItems];
+#pragma unroll
+        for (int it = 0; it < kMaxItems; ++it) {
+            const int p = tid + it * kBlock;
+            mfv[it] = (it < nit && p < KG) ? mf[p] : 0.f;
+        }
         double a1[kMaxItems], a2[kMaxItems];
 #pragma unroll
         for (int it = 0; it < kMaxItems; ++it) a1[it] = a2[it] = 0.0;
         double t0 = 0.0, hh = 0.0;
-        const int64_t r0 = (int64_t)chunk * kChunkRows;
-        const int64_t r1 = min(s.N, r0 + kChunkRows);
+        const int64_t r0 = d.row0 + (int64_t)(chunk - d.chunk0) * kChunkRows;
+        const int64_t r1 = d.row0 + min((int64_t)d.N, (int64_t)(chunk - d.chunk0 + 1) * kChunkRows);
         for (int64_t t = r0; t < r1; t += TR) {
             const int nr = (int)min((int64_t)TR, r1 - t);
-            const float *src = x + t * G;
+            const float *src = bf.x + t * G;
             const int tot = nr * G;
             for (int i = tid; i < tot; i += kBlock) {
                 const int rr = i / G;
@@ -165,10 +195,10 @@ __global__ __launch_bounds__(kBlock) void k_estep_stats(Shape s, const float *__
                     for (int j = 0; j < nr; ++j) {
                         const float rr = rs[j * RS + k];
                         if (rr != 0.f) {
-                            const float d = xs[j * XS + g] - c;
-                            const float w = rr * d;
+                            const float dd = xs[j * XS + g] - c;
+                            const float w = rr * dd;
                             s1 += w;
-                            s2 = fmaf(w, d, s2);
+                            s2 = fmaf(w, dd, s2);
                         }
                     }
                     a1[it] += (double)s1;
@@ -188,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_estep_stats(Shape s, const float *__
             if (tid < off) red[tid] += red[tid + off];
             __syncthreads();
         }
-        double *out = partials + (size_t)chunk * s.S;
+        double *out = bf.partials + (size_t)chunk * s.Smax;
         if (tid < K) out[tid] = t0;
 #pragma unroll
         for (int it = 0; it < kMaxItems; ++it) {
@@ -203,58 +233,83 @@ __global__ __launch_bounds__(kBlock) void k_estep_stats(Shape s, const float *__
     }
 }
 
-__global__ void k_ctl_begin(Ctl *ctl, int max_call, int stop_on_conv, double tol, int reset)
+// ---------------------------------------------------------------------------------------------
+__global__ void k_ctl_begin(int B, Ctl *ctl, int max_call, int stop_on_conv, double tol, int reset)
 {
-    ctl->max_call = max_call;
-    ctl->stop_on_conv = stop_on_conv;
-    ctl->tol = tol;
-    ctl->call_sweeps = 0;
-    ctl->converged = 0;
-    ctl->numeric = 0;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    Ctl *c = ctl + b;
+    c->max_call = max_call;
+    c->stop_on_conv = stop_on_conv;
+    c->tol = tol;
+    c->call_sweeps = 0;
+    c->converged = 0;
+    c->numeric = 0;
     if (reset) {
-        ctl->sweeps = 0;
-        ctl->elbo = 0.0;
-        ctl->elbo_prev = 0.0;
+        c->sweeps = 0;
+        c->elbo = 0.0;
+        c->elbo_prev = 0.0;
     }
 }
 
-// ---------------------------------------------------------------------------------------------
-// Prior centre m0 = per-gene mean of X: per-chunk FP64 column sums, then a
-// fixed-order sum over chunks.
-__global__ __launch_bounds__(kBlock) void k_colpart(Shape s, const float *__restrict__ x, double *__restrict__ colpart)
+// number of datasets that would still sweep
+__global__ void k_count_active(int B, const Ctl *ctl, int32_t *count)
 {
-    const int G = s.G;
-    const int64_t r0 = (int64_t)blockIdx.x * kChunkRows, r1 = min(s.N, r0 + kChunkRows);
+    __shared__ int red[kBlock];
+    int n = 0;
+    for (int b = threadIdx.x; b < B; b += kBlock) n += sweep_skipped(ctl + b) ? 0 : 1;
+    red[threadIdx.x] = n;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = red[0];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Prior centre m0 = per-gene mean of each dataset: per-chunk FP64 column
+// sums, then a fixed-order sum over the dataset's chunks.
+__global__ __launch_bounds__(kBlock) void k_colpart(Shape s, Bufs bf)
+{
+    const int chunk = blockIdx.x, G = s.G;
+    const Ds d = bf.ds[bf.chunk_ds[chunk]];
+    const int64_t r0 = d.row0 + (int64_t)(chunk - d.chunk0) * kChunkRows;
+    const int64_t r1 = d.row0 + min((int64_t)d.N, (int64_t)(chunk - d.chunk0 + 1) * kChunkRows);
     for (int g = threadIdx.x; g < G; g += kBlock) {
         double acc = 0.0;
-        for (int64_t r = r0; r < r1; ++r) acc += (double)x[r * G + g];
-        colpart[(size_t)blockIdx.x * G + g] = acc;
+        for (int64_t r = r0; r < r1; ++r) acc += (double)bf.x[r * G + g];
+        bf.colpart[(size_t)chunk * G + g] = acc;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_colmean(Shape s, const double *__restrict__ colpart, double *__restrict__ m0)
+__global__ __launch_bounds__(kBlock) void k_colmean(Shape s, Bufs bf)
 {
-    for (int g = threadIdx.x; g < s.G; g += kBlock) {
+    const int bi = blockIdx.x, G = s.G;
+    const Ds d = bf.ds[bi];
+    for (int g = threadIdx.x; g < G; g += kBlock) {
         double acc = 0.0;
-        for (int c = 0; c < s.nchunk; ++c) acc += colpart[(size_t)c * s.G + g];
-        m0[g] = acc / (double)s.N;
+        for (int c = d.chunk0; c < d.chunk0 + d.nchunk; ++c) acc += bf.colpart[(size_t)c * G + g];
+        bf.m0[(size_t)bi * G + g] = acc / (double)d.N;
     }
 }
 
 // ---------------------------------------------------------------------------------------------
-// k-means++ helpers: running minimum of the squared distance to the seeds
-// chosen so far, its per-block maximum, and per-block sums of the integer
+// k-means++ helpers for one dataset, driven from the host: running minimum of
+// the squared distance to the seeds chosen so far (mind2, indexed by the
+// dataset's row), its per-block maximum, and per-block sums of the integer
 // weights floor(minD2 * 2^e).
-__global__ __launch_bounds__(kBlock) void k_d2(Shape s, const float *__restrict__ x, const float *__restrict__ seed,
-                                               double *__restrict__ mind2, double *__restrict__ blockmax, int first)
+__global__ __launch_bounds__(kBlock) void k_d2(Shape s, Bufs bf, int bi, int seed_index, int first)
 {
     __shared__ double red[kBlock];
+    const Ds d = bf.ds[bi];
     const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const float *seed = bf.seeds + ((size_t)bi * s.Kmax + seed_index) * s.G;
     double v = 0.0;
-    if (n < s.N) {
-        const double d2 = sqdist64(x + n * s.G, seed, s.G);
-        v = first ? d2 : fmin(mind2[n], d2);
-        mind2[n] = v;
+    if (n < d.N) {
+        const double d2 = sqdist64(bf.x + (d.row0 + n) * s.G, seed, s.G);
+        v = first ? d2 : fmin(bf.mind2[n], d2);
+        bf.mind2[n] = v;
     }
     red[threadIdx.x] = v;
     __syncthreads();
@@ -262,36 +317,127 @@ __global__ __launch_bounds__(kBlock) void k_d2(Shape s, const float *__restrict_
         if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) blockmax[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) bf.blockmax[blockIdx.x] = red[0];
 }
 
-__global__ __launch_bounds__(kBlock) void k_wsum(Shape s, const double *__restrict__ mind2, int e,
-                                                 unsigned long long *__restrict__ blocksum)
+__global__ __launch_bounds__(kBlock) void k_wsum(Shape s, Bufs bf, int bi, int e)
 {
     __shared__ unsigned long long red[kBlock];
+    const Ds d = bf.ds[bi];
     const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     unsigned long long w = 0;
-    if (n < s.N) w = (unsigned long long)floor(ldexp(mind2[n], e));
+    if (n < d.N) w = (unsigned long long)floor(ldexp(bf.mind2[n], e));
     red[threadIdx.x] = w;
     __syncthreads();
     for (int off = kBlock / 2; off > 0; off >>= 1) {
         if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) blocksum[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) bf.blocksum[blockIdx.x] = red[0];
 }
 
 // ---------------------------------------------------------------------------------------------
-// Responsibilities of the current coefficients, one thread per row.
+// k-means++ seeds of every dataset, one workgroup per dataset, with the same
+// definition as the host-driven path: first seed row floor(u N), then the
+// smallest row whose cumulative integer weight floor(minD2 2^e) exceeds
+// floor(u W), with e the largest exponent keeping W below 2^62.  Thread t
+// owns a contiguous segment of rows so the cumulative sum follows row order.
+__global__ __launch_bounds__(kBlock) void k_kmeanspp_batch(Shape s, Bufs bf, const unsigned long long *rng_seeds)
+{
+    __shared__ double dred[kBlock];
+    __shared__ unsigned long long ured[kBlock];
+    __shared__ int64_t pick;
+    const int bi = blockIdx.x, tid = threadIdx.x, G = s.G;
+    const Ds d = bf.ds[bi];
+    const int64_t N = d.N;
+    const float *xb = bf.x + d.row0 * G;
+    double *mind = bf.mind2 + d.row0;
+    float *seeds = bf.seeds + (size_t)bi * s.Kmax * G;
+    unsigned long long rng = rng_seeds[bi];
+    int clog2n = 0;
+    while (((int64_t)1 << clog2n) < N) ++clog2n;
+    const int64_t seg = (N + kBlock - 1) / kBlock;
+    const int64_t n0 = min(N, seg * tid), n1 = min(N, seg * (tid + 1));
+
+    int64_t row = (int64_t)scaled_draw(rng, (unsigned long long)N);
+    for (int j = 0; j < d.K; ++j) {
+        if (j > 0) {
+            // maximum of the running minimum
+            double mx = 0.0;
+            for (int64_t n = n0; n < n1; ++n) mx = fmax(mx, mind[n]);
+            dred[tid] = mx;
+            __syncthreads();
+            for (int off = kBlock / 2; off > 0; off >>= 1) {
+                if (tid < off) dred[tid] = fmax(dred[tid], dred[tid + off]);
+                __syncthreads();
+            }
+            mx = dred[0];
+            __syncthreads();
+            if (mx == 0.0) {
+                row = (int64_t)scaled_draw(rng, (unsigned long long)N);
+            } else {
+                int E;
+                frexp(mx, &E);
+                const int e = 62 - E - clog2n;
+                unsigned long long ws = 0;
+                for (int64_t n = n0; n < n1; ++n) ws += (unsigned long long)floor(ldexp(mind[n], e));
+                ured[tid] = ws;
+                __syncthreads();
+                if (tid == 0) {
+                    unsigned long long W = 0;
+                    for (int i = 0; i < kBlock; ++i) W += ured[i];
+                    const unsigned long long t = scaled_draw(rng, W);
+                    // segment holding the draw, then the row within it
+                    unsigned long long cum = 0;
+                    int seg_i = kBlock - 1;
+                    for (int i = 0; i < kBlock; ++i) {
+                        if (cum + ured[i] > t) {
+                            seg_i = i;
+                            break;
+                        }
+                        cum += ured[i];
+                    }
+                    int64_t r = min(N, seg * (seg_i + 1)) - 1;
+                    for (int64_t n = min(N, seg * seg_i); n < min(N, seg * (seg_i + 1)); ++n) {
+                        cum += (unsigned long long)floor(ldexp(mind[n], e));
+                        if (cum > t) {
+                            r = n;
+                            break;
+                        }
+                    }
+                    pick = r;
+                } else {
+                    // keep the generator state in step on every thread
+                    (void)scaled_draw(rng, 1);
+                }
+                __syncthreads();
+                row = pick;
+                __syncthreads();
+            }
+        }
+        for (int g = tid; g < G; g += kBlock) seeds[(size_t)j * G + g] = xb[row * G + g];
+        __syncthreads();
+        for (int64_t n = n0; n < n1; ++n) {
+            const double d2 = sqdist64(xb + n * G, seeds + (size_t)j * G, G);
+            mind[n] = (j == 0) ? d2 : fmin(mind[n], d2);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Responsibilities of the current coefficients, one thread per row; r is
+// Ntot x Kmax (row-major), entries k >= K of a dataset are left untouched.
 template <int KT>
-__global__ __launch_bounds__(kBlock) void k_resp(Shape s, const float *__restrict__ x, const float *__restrict__ cc,
-                                                 const float2 *__restrict__ hq, float *__restrict__ r)
+__global__ __launch_bounds__(kBlock) void k_resp(Shape s, Bufs bf, float *__restrict__ r)
 {
     const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (n >= s.N) return;
-    const int K = s.K;
+    if (n >= s.Ntot) return;
+    const int bi = dataset_of_row(bf.ds, s.B, n);
+    const int K = bf.ds[bi].K;
+    const size_t kb = (size_t)bi * s.Kmax;
     float l[KT];
-    row_loglik<KT>(x + n * s.G, s.G, K, hq, cc, l);
+    row_loglik<KT>(bf.x + n * s.G, s.G, K, (const float2 *)bf.hq + kb * s.G, bf.cc + kb, l);
     float mx = l[0];
 #pragma unroll
     for (int k = 1; k < KT; ++k)
@@ -305,7 +451,7 @@ __global__ __launch_bounds__(kBlock) void k_resp(Shape s, const float *__restric
     for (int k = 0; k < KT; ++k) {
         if (k < K) {
             const float dl = l[k] - L;
-            r[n * K + k] = dl > -kLogRCut ? __expf(dl) : 0.f;
+            r[n * s.Kmax + k] = dl > -kLogRCut ? __expf(dl) : 0.f;
         }
     }
 }
@@ -332,31 +478,36 @@ static size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
 
 size_t workspace_bytes(const Shape &s)
 {
-    const size_t K = s.K, KG = (size_t)s.K * s.G, G = s.G;
+    const size_t B = s.B, K = (size_t)s.B * s.Kmax, KG = K * s.G, G = s.G;
+    const size_t nblk = (s.Nmax + kBlock - 1) / kBlock;
     size_t n = 0;
+    n += al(B * sizeof(Ds)) + al((size_t)s.nchunk * 4);
     n += 2 * al(K * 8);                // alpha, nalpha
-    n += 9 * al(KG * 8);               // m beta a b, nm nbeta na nb, tmp
-    n += al(G * 8);                    // m0
+    n += 8 * al(KG * 8);               // m beta a b, nm nbeta na nb
+    n += al(B * G * 8);                // m0
     n += al(K * 4) + al(2 * KG * 4) + 2 * al(KG * 4);  // cc, hq, mf, seeds
-    n += al((size_t)s.nchunk * s.S * 8);
-    n += al((size_t)s.S * 8);
-    n += al((size_t)kHist * 8);
-    n += al(sizeof(Ctl));
-    n += al((size_t)s.N * 8);
-    n += al((size_t)s.nblk * 8) * 2;
+    n += al((size_t)s.nchunk * s.Smax * 8);
+    n += al(B * s.Smax * 8);
+    n += al(B * s.hist_cap * 8);
+    n += al(B * sizeof(Ctl)) + al(4);
+    n += al((size_t)s.Ntot * 8);
+    n += 2 * al(nblk * 8);
     n += al((size_t)s.nchunk * G * 8);
     return n;
 }
 
 void carve(const Shape &s, void *ws, Bufs &b)
 {
-    const size_t K = s.K, KG = (size_t)s.K * s.G, G = s.G;
+    const size_t B = s.B, K = (size_t)s.B * s.Kmax, KG = K * s.G, G = s.G;
+    const size_t nblk = (s.Nmax + kBlock - 1) / kBlock;
     char *p = (char *)ws;
     auto take = [&](size_t bytes) {
         void *r = p;
         p += al(bytes);
         return r;
     };
+    b.ds = (const Ds *)take(B * sizeof(Ds));
+    b.chunk_ds = (const int32_t *)take((size_t)s.nchunk * 4);
     b.alpha = (double *)take(K * 8);
     b.nalpha = (double *)take(K * 8);
     b.m = (double *)take(KG * 8);
@@ -367,30 +518,23 @@ void carve(const Shape &s, void *ws, Bufs &b)
     b.nbeta = (double *)take(KG * 8);
     b.na = (double *)take(KG * 8);
     b.nb = (double *)take(KG * 8);
-    b.tmp = (double *)take(KG * 8);
-    b.m0 = (double *)take(G * 8);
+    b.m0 = (double *)take(B * G * 8);
     b.cc = (float *)take(K * 4);
     b.hq = (float *)take(2 * KG * 4);
     b.mf = (float *)take(KG * 4);
     b.seeds = (float *)take(KG * 4);
-    b.partials = (double *)take((size_t)s.nchunk * s.S * 8);
-    b.totals = (double *)take((size_t)s.S * 8);
-    b.hist = (double *)take((size_t)kHist * 8);
-    b.ctl = (Ctl *)take(sizeof(Ctl));
-    b.mind2 = (double *)take((size_t)s.N * 8);
-    b.blockmax = (double *)take((size_t)s.nblk * 8);
-    b.blocksum = (unsigned long long *)take((size_t)s.nblk * 8);
+    b.partials = (double *)take((size_t)s.nchunk * s.Smax * 8);
+    b.totals = (double *)take(B * s.Smax * 8);
+    b.hist = (double *)take(B * s.hist_cap * 8);
+    b.ctl = (Ctl *)take(B * sizeof(Ctl));
+    b.count = (int32_t *)take(4);
+    b.mind2 = (double *)take((size_t)s.Ntot * 8);
+    b.blockmax = (double *)take(nblk * 8);
+    b.blocksum = (unsigned long long *)take(nblk * 8);
     b.colpart = (double *)take((size_t)s.nchunk * G * 8);
 }
 
-template <int KT>
-static hipError_t launch_estep_t(const Shape &s, const Bufs &b, int init_mode, hipStream_t st)
-{
-    const size_t lds = (size_t)s.tile_rows * (s.G + 1 + KT + 1) * sizeof(float);
-    hipLaunchKernelGGL(k_estep_stats<KT>, dim3(s.nchunk), dim3(kBlock), lds, st, s, b.x, b.cc,
-                       (const float2 *)b.hq, b.mf, b.seeds, b.partials, b.ctl, init_mode);
-    return hipGetLastError();
-}
+int g_lds_limit = 0;
 
 hipError_t prepare_kernels()
 {
@@ -405,7 +549,7 @@ hipError_t prepare_kernels()
     g_lds_limit = per_block > optin ? per_block : optin;
     // Raising the dynamic limit is only needed (and only accepted) where the
     // opt-in limit exceeds the default one; failures here are not fatal, the
-    // tile size below is chosen against the limit that the device reports.
+    // tile size is chosen against the limit that the device reports.
     if (optin > per_block) {
         const int want = optin - 4096;
         (void)hipFuncSetAttribute((const void *)k_estep_stats<4>, hipFuncAttributeMaxDynamicSharedMemorySize, want);
@@ -419,11 +563,17 @@ hipError_t prepare_kernels()
     return hipSuccess;
 }
 
-int g_lds_limit = 0;
+template <int KT>
+static hipError_t launch_estep_t(const Shape &s, const Bufs &b, int init_mode, hipStream_t st)
+{
+    const size_t lds = (size_t)s.tile_rows * (s.G + 1 + KT + 1) * sizeof(float);
+    hipLaunchKernelGGL(k_estep_stats<KT>, dim3(s.nchunk), dim3(kBlock), lds, st, s, b, init_mode);
+    return hipGetLastError();
+}
 
 hipError_t launch_estep_stats(const Shape &s, const Bufs &b, int init_mode, hipStream_t st)
 {
-    if (!init_mode && tiled_supported(s.K, s.G)) return launch_estep_tiled(s, b, st);
+    if (!init_mode && tiled_supported(s.Kmax, s.G)) return launch_estep_tiled(s, b, st);
     switch (s.kt) {
     case 4: return launch_estep_t<4>(s, b, init_mode, st);
     case 8: return launch_estep_t<8>(s, b, init_mode, st);
@@ -433,47 +583,59 @@ hipError_t launch_estep_stats(const Shape &s, const Bufs &b, int init_mode, hipS
     }
 }
 
-
-
-
 hipError_t launch_prior_mean(const Shape &s, const Bufs &b, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_colpart, dim3(s.nchunk), dim3(kBlock), 0, st, s, b.x, b.colpart);
+    hipLaunchKernelGGL(k_colpart, dim3(s.nchunk), dim3(kBlock), 0, st, s, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_colmean, dim3(1), dim3(kBlock), 0, st, s, b.colpart, b.m0);
+    hipLaunchKernelGGL(k_colmean, dim3(s.B), dim3(kBlock), 0, st, s, b);
     return hipGetLastError();
 }
 
-hipError_t launch_d2(const Shape &s, const Bufs &b, int seed_index, int first, hipStream_t st)
+hipError_t launch_d2(const Shape &s, const Bufs &b, int dataset, int seed_index, int first, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_d2, dim3(s.nblk), dim3(kBlock), 0, st, s, b.x, b.seeds + (size_t)seed_index * s.G, b.mind2,
-                       b.blockmax, first);
+    const int nblk = (int)((s.Nmax + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_d2, dim3(nblk), dim3(kBlock), 0, st, s, b, dataset, seed_index, first);
     return hipGetLastError();
 }
 
-hipError_t launch_wsum(const Shape &s, const Bufs &b, int e, hipStream_t st)
+hipError_t launch_wsum(const Shape &s, const Bufs &b, int dataset, int e, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_wsum, dim3(s.nblk), dim3(kBlock), 0, st, s, b.mind2, e, b.blocksum);
+    const int nblk = (int)((s.Nmax + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_wsum, dim3(nblk), dim3(kBlock), 0, st, s, b, dataset, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_kmeanspp_batch(const Shape &s, const Bufs &b, const unsigned long long *seeds_dev, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_kmeanspp_batch, dim3(s.B), dim3(kBlock), 0, st, s, b, seeds_dev);
     return hipGetLastError();
 }
 
 hipError_t launch_resp(const Shape &s, const Bufs &b, float *r, hipStream_t st)
 {
-    const dim3 grid(s.nblk);
+    const dim3 grid((unsigned)((s.Ntot + kBlock - 1) / kBlock));
     switch (s.kt) {
-    case 4: hipLaunchKernelGGL(k_resp<4>, grid, dim3(kBlock), 0, st, s, b.x, b.cc, (const float2 *)b.hq, r); break;
-    case 8: hipLaunchKernelGGL(k_resp<8>, grid, dim3(kBlock), 0, st, s, b.x, b.cc, (const float2 *)b.hq, r); break;
-    case 16: hipLaunchKernelGGL(k_resp<16>, grid, dim3(kBlock), 0, st, s, b.x, b.cc, (const float2 *)b.hq, r); break;
-    case 32: hipLaunchKernelGGL(k_resp<32>, grid, dim3(kBlock), 0, st, s, b.x, b.cc, (const float2 *)b.hq, r); break;
-    default: hipLaunchKernelGGL(k_resp<64>, grid, dim3(kBlock), 0, st, s, b.x, b.cc, (const float2 *)b.hq, r); break;
+    case 4: hipLaunchKernelGGL(k_resp<4>, grid, dim3(kBlock), 0, st, s, b, r); break;
+    case 8: hipLaunchKernelGGL(k_resp<8>, grid, dim3(kBlock), 0, st, s, b, r); break;
+    case 16: hipLaunchKernelGGL(k_resp<16>, grid, dim3(kBlock), 0, st, s, b, r); break;
+    case 32: hipLaunchKernelGGL(k_resp<32>, grid, dim3(kBlock), 0, st, s, b, r); break;
+    default: hipLaunchKernelGGL(k_resp<64>, grid, dim3(kBlock), 0, st, s, b, r); break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_ctl_begin(const Bufs &b, int max_call, int stop_on_conv, double tol, int reset, hipStream_t st)
+hipError_t launch_ctl_begin(const Shape &s, const Bufs &b, int max_call, int stop_on_conv, double tol, int reset,
+                            hipStream_t st)
 {
-    hipLaunchKernelGGL(k_ctl_begin, dim3(1), dim3(1), 0, st, b.ctl, max_call, stop_on_conv, tol, reset);
+    hipLaunchKernelGGL(k_ctl_begin, dim3((s.B + 255) / 256), dim3(256), 0, st, s.B, b.ctl, max_call, stop_on_conv,
+                       tol, reset);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_active(const Shape &s, const Bufs &b, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(kBlock), 0, st, s.B, b.ctl, b.count);
     return hipGetLastError();
 }
 

@@ -118,16 +118,10 @@ __device__ __forceinline__ double wave_sum(double v)
 }  // namespace
 
 template <int KT, int G>
-__global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, const float *__restrict__ x,
-                                                           const float *__restrict__ cc,
-                                                           const float *__restrict__ hq,
-                                                           const float *__restrict__ mf,
-                                                           double *__restrict__ partials,
-                                                           const Ctl *__restrict__ ctl)
+__global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
 {
     using C = Cfg<KT, G>;
     constexpr int XS = C::XS, LS = C::LS, PS = C::PS, KQ = C::KQ, GS = C::GS, GB = C::GB, HG = C::HG;
-    if (sweep_skipped(ctl)) return;
     extern __shared__ __align__(16) float smem[];
     float *xs = smem;                 // kT x XS   x tile
     float *ls = xs + kT * XS;         // kT x LS   partial, then exact, row log-likelihood sums
@@ -137,27 +131,37 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, const float 
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int K = s.K, KG = K * G;
-
-    for (int i = tid; i < KT * G; i += kBlock) {
-        const int k = i / G, g = i - k * G;
-        pt[k * PS + 2 * g] = k < K ? hq[2 * i] : 0.f;
-        pt[k * PS + 2 * g + 1] = k < K ? hq[2 * i + 1] : 0.f;
-    }
-    if (tid < KT) ccs[tid] = tid < K ? cc[tid] : 0.f;
-    float mfv[KT][GS];
-#pragma unroll
-    for (int k = 0; k < KT; ++k)
-#pragma unroll
-        for (int sl = 0; sl < GS; ++sl) {
-            const int g = lane + 64 * sl;
-            mfv[k][sl] = (k < K && g < G) ? mf[k * G + g] : 0.f;
-        }
-
     const int jl = lane & 31, half = lane >> 5;
+    const float *__restrict__ x = bf.x;
+
     for (int chunk = blockIdx.x; chunk < s.nchunk; chunk += gridDim.x) {
-        const int64_t r0 = (int64_t)chunk * kChunkRows;
-        const int nrc = (int)min((int64_t)kChunkRows, s.N - r0);
+        const int bi = bf.chunk_ds[chunk];
+        const Ds d = bf.ds[bi];
+        if (sweep_skipped(bf.ctl + bi)) continue;
+        const int K = d.K, KG = K * G;
+        const size_t kb = (size_t)bi * s.Kmax;
+        const float *__restrict__ cc = bf.cc + kb;
+        const float *__restrict__ hq = bf.hq + 2 * kb * G;
+        const float *__restrict__ mf = bf.mf + kb * G;
+        double *__restrict__ partials = bf.partials;
+
+        for (int i = tid; i < KT * G; i += kBlock) {
+            const int k = i / G, g = i - k * G;
+            pt[k * PS + 2 * g] = k < K ? hq[2 * i] : 0.f;
+            pt[k * PS + 2 * g + 1] = k < K ? hq[2 * i + 1] : 0.f;
+        }
+        if (tid < KT) ccs[tid] = tid < K ? cc[tid] : 0.f;
+        float mfv[KT][GS];
+#pragma unroll
+        for (int k = 0; k < KT; ++k)
+#pragma unroll
+            for (int sl = 0; sl < GS; ++sl) {
+                const int g = lane + 64 * sl;
+                mfv[k][sl] = (k < K && g < G) ? mf[k * G + g] : 0.f;
+            }
+
+        const int64_t r0 = d.row0 + (int64_t)(chunk - d.chunk0) * kChunkRows;
+        const int nrc = (int)min((int64_t)kChunkRows, (int64_t)d.N - (int64_t)(chunk - d.chunk0) * kChunkRows);
         const int ntiles = (nrc + kT - 1) / kT;
 
         float t0[KT], t1[KT][GS], t2[KT][GS];
@@ -393,7 +397,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, const float 
             if (tid < off) red[tid] += red[tid + off];
             lds_barrier();
         }
-        double *out = partials + (size_t)chunk * s.S;
+        double *out = partials + (size_t)chunk * s.Smax;
         for (int i = tid; i < K + 2 * KG; i += kBlock) out[i] = cb[i];
         if (tid == 0) out[K + 2 * KG] = red[0];
         lds_barrier();
@@ -406,8 +410,7 @@ template <int KT, int G>
 hipError_t launch_t(const Shape &s, const Bufs &b, hipStream_t st)
 {
     constexpr int lds = Cfg<KT, G>::LDS_BYTES;
-    hipLaunchKernelGGL((k_estep_tiled<KT, G>), dim3(s.nchunk), dim3(kBlock), lds, st, s, b.x, b.cc, b.hq, b.mf,
-                       b.partials, b.ctl);
+    hipLaunchKernelGGL((k_estep_tiled<KT, G>), dim3(s.nchunk), dim3(kBlock), lds, st, s, b);
     return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
-// Global step of a sweep: fixed-order reduction of the chunk statistics, the
-// conjugate updates (forms of eqs 16, 17 and 24), the lower bound (eqs
-// 10-11), the convergence test, and the FP32 coefficients of the next E-step
-// (expectations of eqs 26-31).
+// Global step of a sweep, per dataset: fixed-order reduction of the chunk
+// statistics, the conjugate updates (forms of eqs 16, 17 and 24), the lower
+// bound (eqs 10-11), the convergence test, and the FP32 coefficients of the
+// next E-step (expectations of eqs 26-31).
 #include <math.h>
 
 #include "cavi_impl.h"
@@ -31,37 +31,74 @@ struct MShared {
     int bad;
 };
 
+// Per-dataset views of the batch arrays.
+struct View {
+    int K, G;
+    double *alpha, *m, *beta, *a, *b;
+    double *nalpha, *nm, *nbeta, *na, *nb;
+    const double *m0;
+    float *cc, *hq, *mf;
+    const double *totals;
+    double *hist;
+    Ctl *ctl;
+};
+
+__device__ __forceinline__ View view(const Shape &s, const Bufs &bf, int bi)
+{
+    View v;
+    const size_t kb = (size_t)bi * s.Kmax, kg = kb * s.G;
+    v.K = bf.ds[bi].K;
+    v.G = s.G;
+    v.alpha = bf.alpha + kb;
+    v.nalpha = bf.nalpha + kb;
+    v.m = bf.m + kg;
+    v.beta = bf.beta + kg;
+    v.a = bf.a + kg;
+    v.b = bf.b + kg;
+    v.nm = bf.nm + kg;
+    v.nbeta = bf.nbeta + kg;
+    v.na = bf.na + kg;
+    v.nb = bf.nb + kg;
+    v.m0 = bf.m0 + (size_t)bi * s.G;
+    v.cc = bf.cc + kb;
+    v.hq = bf.hq + 2 * kg;
+    v.mf = bf.mf + kg;
+    v.totals = bf.totals + (size_t)bi * s.Smax;
+    v.hist = bf.hist + (size_t)bi * s.hist_cap;
+    v.ctl = bf.ctl + bi;
+    return v;
+}
+
 // Per-(k,g) coefficients of the E-step from one subpopulation-gene state:
 //   l_nk = c_k - sum_g (h x + q)^2,  h = sqrt(E[tau]/2),  q = -m h,
 //   c_k  = E ln pi_k + sum_g tmp_kg,  tmp = (E ln tau - ln 2pi - 1/beta) / 2.
-__device__ __forceinline__ double coef_item(const Bufs &b, int q, double mm, double bt, double aa, double bb,
+__device__ __forceinline__ double coef_item(const View &v, int q, double mm, double bt, double aa, double bb,
                                             double elt)
 {
     const float hf = (float)sqrt(0.5 * aa / bb);
-    b.hq[2 * q] = hf;
-    b.hq[2 * q + 1] = (float)(-mm * (double)hf);
-    b.mf[q] = (float)mm;
+    v.hq[2 * q] = hf;
+    v.hq[2 * q + 1] = (float)(-mm * (double)hf);
+    v.mf[q] = (float)mm;
     return 0.5 * (elt - kLn2Pi - 1.0 / bt);
 }
 
 // c_k from the per-(k,g) parts in LDS: wave w sums subpopulations w, w+4, ...
-__device__ __forceinline__ void coef_rows(const Shape &s, const Bufs &b, MShared &sh, const Prior *p,
-                                          const double *T0, int with_bound)
+__device__ __forceinline__ void coef_rows(const View &v, MShared &sh, const Prior *p, int with_bound)
 {
-    const int G = s.G, K = s.K;
+    const int G = v.G, K = v.K;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int k = wv; k < K; k += kBlock / 64) {
-        double v = 0.0;
-        for (int g = lane; g < G; g += 64) v += sh.tmp[k * G + g];
-        v = wave_sum(v);
+        double x = 0.0;
+        for (int g = lane; g < G; g += 64) x += sh.tmp[k * G + g];
+        x = wave_sum(x);
         if (lane == 0) {
             const double elnpi = sh.psi_ak[k] - sh.psum;
-            const double c = elnpi + v;
-            b.cc[k] = (float)c;
+            const double c = elnpi + x;
+            v.cc[k] = (float)c;
             if (!isfinite(c)) sh.bad = 1;
             if (with_bound) {
                 const double ak = sh.ak[k];
-                sh.term_k[k] = T0[k] * elnpi + (p->alpha0 - 1.0) * elnpi + sh.lg_ak[k] - (ak - 1.0) * elnpi;
+                sh.term_k[k] = v.totals[k] * elnpi + (p->alpha0 - 1.0) * elnpi + sh.lg_ak[k] - (ak - 1.0) * elnpi;
             }
         }
     }
@@ -69,30 +106,33 @@ __device__ __forceinline__ void coef_rows(const Shape &s, const Bufs &b, MShared
 
 }  // namespace
 
-// totals[i] = sum over chunks of partials[chunk][i] in a fixed order: wave v of
-// the block sums a contiguous 1/16 of the chunks (4 interleaved accumulators),
-// then the 16 wave sums are added in wave order.
-__global__ __launch_bounds__(kRedBlock) void k_reduce(const double *__restrict__ partials, int nchunk, int S,
-                                                      double *__restrict__ totals, const Ctl *__restrict__ ctl,
-                                                      int init_mode)
+// totals[b][i] = sum over the chunks of dataset b of partials[chunk][i], in a
+// fixed order: wave v of the block sums a contiguous 1/16 of the chunks (4
+// interleaved accumulators), then the 16 wave sums are added in wave order.
+__global__ __launch_bounds__(kRedBlock) void k_reduce(Shape s, Bufs bf, int init_mode)
 {
-    if (!init_mode && sweep_skipped(ctl)) return;
+    const int bi = blockIdx.y;
+    if (!init_mode && sweep_skipped(bf.ctl + bi)) return;
+    const Ds d = bf.ds[bi];
+    const int S = d.K + 2 * d.K * s.G + 1;
     __shared__ double part[kRedBlock / 64][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int nw = kRedBlock / 64;
     const int i = blockIdx.x * 64 + lane;
+    if (blockIdx.x * 64 >= S) return;
+    const double *pp = bf.partials + (size_t)d.chunk0 * s.Smax;
     double acc = 0.0;
     if (i < S) {
-        const int c0 = (int)(((int64_t)nchunk * wv) / nw), c1 = (int)(((int64_t)nchunk * (wv + 1)) / nw);
+        const int c0 = (int)(((int64_t)d.nchunk * wv) / nw), c1 = (int)(((int64_t)d.nchunk * (wv + 1)) / nw);
         double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
         int c = c0;
         for (; c + 4 <= c1; c += 4) {
-            q0 += partials[(size_t)c * S + i];
-            q1 += partials[(size_t)(c + 1) * S + i];
-            q2 += partials[(size_t)(c + 2) * S + i];
-            q3 += partials[(size_t)(c + 3) * S + i];
+            q0 += pp[(size_t)c * s.Smax + i];
+            q1 += pp[(size_t)(c + 1) * s.Smax + i];
+            q2 += pp[(size_t)(c + 2) * s.Smax + i];
+            q3 += pp[(size_t)(c + 3) * s.Smax + i];
         }
-        for (; c < c1; ++c) q0 += partials[(size_t)c * S + i];
+        for (; c < c1; ++c) q0 += pp[(size_t)c * s.Smax + i];
         acc = (q0 + q1) + (q2 + q3);
     }
     part[wv][lane] = acc;
@@ -100,30 +140,31 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce(const double *__restrict__
     if (wv == 0 && i < S) {
         double t = part[0][lane];
         for (int v = 1; v < nw; ++v) t += part[v][lane];
-        totals[i] = t;
+        bf.totals[(size_t)bi * s.Smax + i] = t;
     }
 }
 
 // Coefficients of the E-step from the committed state (after set_state).
-__global__ __launch_bounds__(kBlock) void k_coef(Shape s, Bufs b)
+__global__ __launch_bounds__(kBlock) void k_coef(Shape s, Bufs bf)
 {
     __shared__ MShared sh;
-    const int tid = threadIdx.x, K = s.K, KG = K * s.G;
+    const View v = view(s, bf, blockIdx.x);
+    const int tid = threadIdx.x, K = v.K, KG = K * v.G;
     if (tid == 0) sh.bad = 0;
-    if (tid < K) sh.psi_ak[tid] = dev_digamma(b.alpha[tid]);
+    if (tid < K) sh.psi_ak[tid] = dev_digamma(v.alpha[tid]);
     for (int q = tid; q < KG; q += kBlock) {
-        const double aa = b.a[q], bb = b.b[q];
-        sh.tmp[q] = coef_item(b, q, b.m[q], b.beta[q], aa, bb, dev_digamma(aa) - log(bb));
+        const double aa = v.a[q], bb = v.b[q];
+        sh.tmp[q] = coef_item(v, q, v.m[q], v.beta[q], aa, bb, dev_digamma(aa) - log(bb));
     }
     __syncthreads();
     if (tid < 64) {
-        double v = 0.0;
-        for (int k = tid; k < K; k += 64) v += b.alpha[k];
-        v = wave_sum(v);
-        if (tid == 0) sh.psum = dev_digamma(v);
+        double x = 0.0;
+        for (int k = tid; k < K; k += 64) x += v.alpha[k];
+        x = wave_sum(x);
+        if (tid == 0) sh.psum = dev_digamma(x);
     }
     __syncthreads();
-    coef_rows(s, b, sh, nullptr, nullptr, 0);
+    coef_rows(v, sh, nullptr, 0);
 }
 
 // Conjugate updates from the totals, written with sums around the E-step's
@@ -133,13 +174,14 @@ __global__ __launch_bounds__(kBlock) void k_coef(Shape s, Bufs b)
 // then the lower bound at the new q(pi), q(mu, tau) with the entropy H of the
 // responsibilities.  A non-finite value leaves the state untouched and raises
 // ctl->numeric.
-__global__ __launch_bounds__(kBlock) void k_mstep(Shape s, Bufs b, Prior p, int init_mode)
+__global__ __launch_bounds__(kBlock) void k_mstep(Shape s, Bufs bf, Prior p, int init_mode)
 {
-    Ctl *ctl = b.ctl;
+    const View v = view(s, bf, blockIdx.x);
+    Ctl *ctl = v.ctl;
     if (!init_mode && sweep_skipped(ctl)) return;
     __shared__ MShared sh;
-    const int G = s.G, K = s.K, KG = K * G, tid = threadIdx.x;
-    const double *T0 = b.totals, *T1 = T0 + K, *T2 = T1 + KG;
+    const int G = v.G, K = v.K, KG = K * G, tid = threadIdx.x;
+    const double *T0 = v.totals, *T1 = T0 + K, *T2 = T1 + KG;
     const double H = T2[KG];
     if (tid == 0) sh.bad = 0;
     if (tid < K) {
@@ -147,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_mstep(Shape s, Bufs b, Prior p, int 
         sh.ak[tid] = a;
         sh.psi_ak[tid] = dev_digamma(a);
         sh.lg_ak[tid] = dev_lgamma(a);
-        b.nalpha[tid] = a;
+        v.nalpha[tid] = a;
     }
     const double half_ln_b0 = 0.5 * log(p.beta0 / kTwoPi);
     const double prior_const = half_ln_b0 + p.a0 * log(p.b0) - dev_lgamma(p.a0);
@@ -156,18 +198,18 @@ __global__ __launch_bounds__(kBlock) void k_mstep(Shape s, Bufs b, Prior p, int 
     for (int q = tid; q < KG; q += kBlock) {
         const int k = q / G, g = q - k * G;
         const double Nk = T0[k];
-        const double c = (double)b.mf[q];
-        const double m0p = b.m0[g] - c;
+        const double c = (double)v.mf[q];
+        const double m0p = v.m0[g] - c;
         const double bt = p.beta0 + Nk;
         const double mp = (p.beta0 * m0p + T1[q]) / bt;
         const double mm = c + mp;
         const double aa = p.a0 + 0.5 * Nk;
         double bb = p.b0 + 0.5 * (T2[q] + p.beta0 * m0p * m0p - bt * mp * mp);
         if (bb < p.b0) bb = p.b0;
-        b.nm[q] = mm;
-        b.nbeta[q] = bt;
-        b.na[q] = aa;
-        b.nb[q] = bb;
+        v.nm[q] = mm;
+        v.nbeta[q] = bt;
+        v.na[q] = aa;
+        v.nb[q] = bb;
         const double elt = dev_digamma(aa) - log(bb);
         const double tb = aa / bb;
         if (!init_mode) {
@@ -179,22 +221,22 @@ __global__ __launch_bounds__(kBlock) void k_mstep(Shape s, Bufs b, Prior p, int 
                    - p.b0 * tb;
             acc -= 0.5 * log(bt / kTwoPi) + 0.5 * elt - 0.5 + aa * log(bb) - dev_lgamma(aa) + (aa - 1.0) * elt - aa;
         }
-        sh.tmp[q] = coef_item(b, q, mm, bt, aa, bb, elt);
+        sh.tmp[q] = coef_item(v, q, mm, bt, aa, bb, elt);
         if (!isfinite(mm) || !isfinite(bb) || !isfinite(elt) || !isfinite(T2[q])) bad = 1;
     }
     if (bad) atomicOr(&sh.bad, 1);
     __syncthreads();
     if (tid < 64) {
-        double v = 0.0;
-        for (int k = tid; k < K; k += 64) v += sh.ak[k];
-        v = wave_sum(v);
+        double x = 0.0;
+        for (int k = tid; k < K; k += 64) x += sh.ak[k];
+        x = wave_sum(x);
         if (tid == 0) {
-            sh.asum = v;
-            sh.psum = dev_digamma(v);
+            sh.asum = x;
+            sh.psum = dev_digamma(x);
         }
     }
     __syncthreads();
-    coef_rows(s, b, sh, &p, T0, !init_mode);
+    coef_rows(v, sh, &p, !init_mode);
     sh.red[tid] = acc;
     __syncthreads();
     for (int off = kBlock / 2; off > 0; off >>= 1) {
@@ -224,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_mstep(Shape s, Bufs b, Prior p, int 
                 if (t >= 2 && fabs(L - ctl->elbo) <= ctl->tol * fabs(L)) ctl->converged = 1;
                 ctl->elbo_prev = ctl->elbo;
                 ctl->elbo = L;
-                b.hist[(t - 1) % kHist] = L;
+                v.hist[(t - 1) % s.hist_cap] = L;
                 ctl->call_sweeps = t;
                 ctl->sweeps += 1;
             }
@@ -232,31 +274,30 @@ __global__ __launch_bounds__(kBlock) void k_mstep(Shape s, Bufs b, Prior p, int 
     }
     __syncthreads();
     if (sh.bad) return;
-    if (tid < K) b.alpha[tid] = b.nalpha[tid];
+    if (tid < K) v.alpha[tid] = v.nalpha[tid];
     for (int q = tid; q < KG; q += kBlock) {
-        b.m[q] = b.nm[q];
-        b.beta[q] = b.nbeta[q];
-        b.a[q] = b.na[q];
-        b.b[q] = b.nb[q];
+        v.m[q] = v.nm[q];
+        v.beta[q] = v.nbeta[q];
+        v.a[q] = v.na[q];
+        v.b[q] = v.nb[q];
     }
 }
 
 hipError_t launch_reduce(const Shape &s, const Bufs &b, int init_mode, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce, dim3((s.S + 63) / 64), dim3(kRedBlock), 0, st, b.partials, s.nchunk, s.S, b.totals,
-                       b.ctl, init_mode);
+    hipLaunchKernelGGL(k_reduce, dim3((s.Smax + 63) / 64, s.B), dim3(kRedBlock), 0, st, s, b, init_mode);
     return hipGetLastError();
 }
 
 hipError_t launch_mstep(const Shape &s, const Bufs &b, const Prior &p, int init_mode, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mstep, dim3(1), dim3(kBlock), 0, st, s, b, p, init_mode);
+    hipLaunchKernelGGL(k_mstep, dim3(s.B), dim3(kBlock), 0, st, s, b, p, init_mode);
     return hipGetLastError();
 }
 
 hipError_t launch_coef(const Shape &s, const Bufs &b, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_coef, dim3(1), dim3(kBlock), 0, st, s, b);
+    hipLaunchKernelGGL(k_coef, dim3(s.B), dim3(kBlock), 0, st, s, b);
     return hipGetLastError();
 }
 

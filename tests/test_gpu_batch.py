@@ -1,0 +1,110 @@
+"""Batched CAVI through the C ABI: each dataset of a batch gives bitwise the
+results of a single-dataset handle over its rows, and matches the oracle."""
+import numpy as np
+import pytest
+
+from oracle import cavi_oracle as oc
+from paper_2401_10068_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2401_10068_amd import cavi
+
+    cavi.lib()
+    return torch
+
+
+def make_batch(seed, Ns, Ks, G, lo=15.0, hi=20.0):
+    xs, m0s = [], []
+    for b, (N, K) in enumerate(zip(Ns, Ks)):
+        rec = synth.Recipe(K=K, G=G, mu_lo=lo, mu_hi=hi)
+        X, *_ = synth.make_dataset(seed, b, N, rec)
+        xs.append(X)
+        m0s.append(oc.data_mean(X))
+    return xs, np.stack(m0s)
+
+
+def single(torch, X, K, m0, state=None, seed=None, sweeps=0):
+    from paper_2401_10068_amd.cavi import Cavi
+
+    cx = Cavi(torch.from_numpy(X).cuda(), K, m0=m0)
+    if state is not None:
+        cx.set_state(*state.arrays())
+    else:
+        cx.init_standard(seed)
+    if sweeps:
+        cx.sweep(sweeps, want_elbo=False)
+    st = cx.get_state()
+    cx.close()
+    return st
+
+
+@pytest.mark.parametrize("G", [48, 7])
+def test_batch_equals_single_bitwise(torch_cuda, G):
+    from paper_2401_10068_amd.cavi import CaviBatch
+
+    Ns = [2048 * 2 + 77, 300, 2048, 5000, 64]
+    Ks = [5, 2, 8, 3, 4]
+    xs, m0 = make_batch(21, Ns, Ks, G)
+    states = [oc.init_standard(X, K, oc.Prior(), m0[b], seed=b) for b, (X, K) in enumerate(zip(xs, Ks))]
+    bt = CaviBatch(torch_cuda.from_numpy(np.concatenate(xs)).cuda(), Ns, Ks, m0=m0)
+    for b, st in enumerate(states):
+        bt.set_state(b, *st.arrays())
+    bt.sweep(20)
+    got = [bt.get_state(b) for b in range(len(Ns))]
+    bt.close()
+    for b, (X, K) in enumerate(zip(xs, Ks)):
+        ref = single(torch_cuda, X, K, m0[b], state=states[b], sweeps=20)
+        for a, r in zip(got[b], ref):
+            assert np.array_equal(a, r), f"dataset {b}"
+
+
+def test_batch_init_matches_single_init(torch_cuda):
+    from paper_2401_10068_amd.cavi import CaviBatch
+
+    Ns = [3000, 700, 2048 * 3 + 5]
+    Ks = [4, 6, 3]
+    G = 48
+    xs, m0 = make_batch(22, Ns, Ks, G, lo=15, hi=35)
+    bt = CaviBatch(torch_cuda.from_numpy(np.concatenate(xs)).cuda(), Ns, Ks, m0=m0)
+    bt.init_standard(100)
+    got = [bt.get_state(b) for b in range(len(Ns))]
+    bt.close()
+    for b, (X, K) in enumerate(zip(xs, Ks)):
+        ref = single(torch_cuda, X, K, m0[b], seed=100 + b)
+        for a, r in zip(got[b], ref):
+            assert np.array_equal(a, r), f"dataset {b}"
+        ost = oc.init_standard(X, K, oc.Prior(), m0[b], 100 + b)
+        np.testing.assert_allclose(got[b][1], ost.m, rtol=1e-6)
+
+
+def test_batch_run_matches_oracle_per_dataset(torch_cuda):
+    from paper_2401_10068_amd.cavi import CaviBatch
+
+    Ns = [1500, 4000, 900, 2500]
+    Ks = [3, 4, 2, 5]
+    G = 48
+    xs, m0 = make_batch(23, Ns, Ks, G, lo=15, hi=17)
+    pr = oc.Prior()
+    states = [oc.init_standard(X, K, pr, m0[b], seed=b) for b, (X, K) in enumerate(zip(xs, Ks))]
+    bt = CaviBatch(torch_cuda.from_numpy(np.concatenate(xs)).cuda(), Ns, Ks, m0=m0)
+    for b, st in enumerate(states):
+        bt.set_state(b, *st.arrays())
+    sw, el, nconv = bt.run(3000, 1e-6)
+    got = [bt.get_state(b) for b in range(len(Ns))]
+    bt.close()
+    assert nconv == len(Ns)
+    for b, (X, K) in enumerate(zip(xs, Ks)):
+        n, conv, tr = oc.run(X, pr, m0[b], states[b], 3000, 1e-6)
+        assert conv
+        assert abs(el[b] - tr[-1]) <= 1e-6 * abs(tr[-1]), b
+        ea = got[b][0] / got[b][0].sum()
+        eo = states[b].alpha / states[b].alpha.sum()
+        np.testing.assert_allclose(ea, eo, atol=1e-4, rtol=0)
+        assert abs(int(sw[b]) - n) <= max(3, 0.1 * n)
