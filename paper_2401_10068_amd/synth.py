@@ -309,3 +309,22 @@ def make_dataset_gpu(seed: int, dataset: int, N: int, recipe: Recipe, want_z: bo
     x, _, _, pi, mu, tau, z = make_batch_gpu(seed, [N], [recipe.K], recipe, ds_offset=dataset, want_z=want_z,
                                              device=device)
     return x, z, pi[0], mu[0], tau[0]
+
+
+def batch_workload(name: str):
+    """Named batched workloads: ``(Ns, Ks, recipe, seed)``.
+
+    * ``c4``       4,096 datasets, N log-uniform in [200, 200,000], K uniform in {2..8},
+                   G=48, Dir(1) proportions, seed 3;
+    * ``c5train``  warm-start training datasets: N log-uniform in [500, 50,000], K=8, G=48, seed 4
+                   (the count is chosen by the caller: ``Ns`` here covers the first 4,096);
+    * ``c5eval``   4,096 fresh datasets of the same distribution, seed 5.
+    """
+    if name == "c4":
+        Ns, Ks = batch_shapes(3, 4096, 200, 200_000, 2, 8)
+        return Ns, Ks, Recipe(K=8, G=48, dir_alpha=1.0), 3
+    if name in ("c5train", "c5eval"):
+        seed = 4 if name == "c5train" else 5
+        Ns, _ = batch_shapes(seed, 4096, 500, 50_000, 8, 8)
+        return Ns, np.full(Ns.size, 8, dtype=np.int32), Recipe(K=8, G=48, dir_alpha=1.0), seed
+    raise KeyError(name)
