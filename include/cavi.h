@@ -162,6 +162,18 @@ cavi_status cavi_batch_init_standard(cavi_batch *bt, uint64_t seed);
  * cavi_set_state).  Coefficients are rebuilt at the next sweep or run. */
 cavi_status cavi_batch_set_state(cavi_batch *bt, int32_t b, const double *alpha, const double *m,
                                  const double *beta, const double *a, const double *bb);
+/* Learned warm start: every dataset's state from the MLP output rows
+ * out_dev (device, FP32, B rows of stride ld >= K(2G+1), dataset order).
+ * Row layout [mu' (K x G) | ln E[tau] (K x G) | proportion logits (K)],
+ * subpopulation-major, mu = 25 + 10 mu'.  With pi = softmax(logits) and
+ * n_k = N pi_k the state is the conjugate posterior those moments give:
+ * alpha_k = alpha0 + n_k, beta = beta0 + n_k, m = mu, a = a0 + n_k / 2,
+ * b = a / E[tau] (ln E[tau] clamped to [-30, 30]).  The paper has no warm
+ * start: this only chooses the starting point of the coordinate updates of
+ * Section 3.4, which then run as from any set state.  Synchronises the
+ * stream. */
+cavi_status cavi_batch_set_state_warm(cavi_batch *bt, const float *out_dev, int32_t ld);
+
 cavi_status cavi_batch_get_state(cavi_batch *bt, int32_t b, double *alpha, double *m, double *beta,
                                  double *a, double *bb);
 
@@ -176,6 +188,61 @@ cavi_status cavi_batch_run(cavi_batch *bt, int32_t max_sweeps, double rel_tol, i
                            double *elbo, int32_t *n_converged);
 
 cavi_status cavi_batch_destroy(cavi_batch *bt);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start (not in the paper; it only supplies the starting state
+ * of the Section 3.4 iteration).  A per-dataset feature vector is mapped by
+ * an MLP to a variational state (cavi_batch_set_state_warm).
+ *
+ * Features (cavi_features): for each dataset b (rows row_off[b] ..
+ * row_off[b+1]-1 of the FP32 device array x_dev, G columns, row_off a DEVICE
+ * int64 array of B+1 offsets) and gene g, 18 values at feat_dev[b*18G + g*18
+ * + j]: j=0 the mean, j=1 ln max(var, 1e-30) (population variance, FP64
+ * sums), j=2..17 the 16 quantiles of the first M = min(N, 4096) rows' values
+ * at ranks floor((2i+1) M / 32), i = 0..15.  Mean and quantiles are stored as
+ * (v - 25)/10, the log-variance as is.  Device output, FP32.
+ *
+ * Targets (cavi_warm_targets): from generating parameters (DEVICE FP64:
+ * pi[B*K], mu[B*K*G], tau[B*K*G], k-major per dataset) the training target
+ * rows target_dev[b*K(2G+1) ..]: subpopulations ordered by their mean over
+ * genes (ascending, ties by index), then [(mu-25)/10 | ln tau | ln pi].
+ *
+ * MLP (cavi_mlp_*): in_dim -> hidden (x n_hidden, exact-erf GELU) -> out_dim
+ * linear.  FP32 master parameters, for each layer l: W_l (out x in,
+ * row-major) then b_l, concatenated; initialised W ~ U(-1/sqrt(in),
+ * 1/sqrt(in)) from SplitMix64(seed), b = 0.  Every product rounds both
+ * operands to BF16 (round to nearest even) and accumulates in FP32 on the
+ * matrix cores; bias, activation, loss and optimiser are FP32.
+ *   forward:   out_dev[B x out_dim] for feat_dev[B x in_dim] (device).
+ *   loss_grad: forward, loss = mean over B*out_dim of (y - t)^2, gradients
+ *              of that loss into the library's gradient buffer (overwritten);
+ *              loss_host (may be NULL) receives the loss (synchronises).
+ *   adamw:     one AdamW step (decoupled weight decay, bias-corrected
+ *              moments, step count kept by the handle).
+ *   get/set_params, get_grads: HOST FP32 arrays of n_params entries
+ *              (synchronise).
+ * B <= max_batch.  Work is enqueued on hip_stream (NULL: a stream the
+ * handle creates).  Not thread-safe.
+ * ------------------------------------------------------------------------ */
+cavi_status cavi_features(const float *x_dev, const int64_t *row_off_dev, int32_t B, int32_t G,
+                          float *feat_dev, void *hip_stream);
+cavi_status cavi_warm_targets(const double *pi_dev, const double *mu_dev, const double *tau_dev,
+                              int32_t B, int32_t K, int32_t G, float *target_dev, void *hip_stream);
+
+typedef struct cavi_mlp cavi_mlp;
+
+cavi_status cavi_mlp_create(cavi_mlp **out, int32_t in_dim, int32_t hidden, int32_t n_hidden,
+                            int32_t out_dim, int32_t max_batch, uint64_t seed, void *hip_stream);
+cavi_status cavi_mlp_n_params(cavi_mlp *net, int64_t *n);
+cavi_status cavi_mlp_get_params(cavi_mlp *net, float *host);
+cavi_status cavi_mlp_set_params(cavi_mlp *net, const float *host);
+cavi_status cavi_mlp_get_grads(cavi_mlp *net, float *host);
+cavi_status cavi_mlp_forward(cavi_mlp *net, const float *feat_dev, int32_t B, float *out_dev);
+cavi_status cavi_mlp_loss_grad(cavi_mlp *net, const float *feat_dev, const float *target_dev, int32_t B,
+                               float *loss_host);
+cavi_status cavi_mlp_adamw(cavi_mlp *net, float lr, float beta1, float beta2, float eps,
+                           float weight_decay);
+cavi_status cavi_mlp_destroy(cavi_mlp *net);
 
 /* Thread-local text of the last error ("" if none). */
 const char *cavi_last_error(void);

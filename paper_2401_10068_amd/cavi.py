@@ -65,6 +65,19 @@ def lib():
             "cavi_batch_sweep": (st, [vp, C.c_int32]),
             "cavi_batch_run": (st, [vp, C.c_int32, C.c_double, vp, vp, C.POINTER(C.c_int32)]),
             "cavi_batch_destroy": (st, [vp]),
+            "cavi_batch_set_state_warm": (st, [vp, vp, C.c_int32]),
+            "cavi_features": (st, [vp, vp, C.c_int32, C.c_int32, vp, vp]),
+            "cavi_warm_targets": (st, [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp]),
+            "cavi_mlp_create": (st, [C.POINTER(vp), C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                     C.c_uint64, vp]),
+            "cavi_mlp_n_params": (st, [vp, C.POINTER(C.c_int64)]),
+            "cavi_mlp_get_params": (st, [vp, vp]),
+            "cavi_mlp_set_params": (st, [vp, vp]),
+            "cavi_mlp_get_grads": (st, [vp, vp]),
+            "cavi_mlp_forward": (st, [vp, vp, C.c_int32, vp]),
+            "cavi_mlp_loss_grad": (st, [vp, vp, vp, C.c_int32, C.POINTER(C.c_float)]),
+            "cavi_mlp_adamw": (st, [vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float]),
+            "cavi_mlp_destroy": (st, [vp]),
             "cavi_last_error": (C.c_char_p, []),
             "cavi_version": (C.c_char_p, []),
         }
@@ -295,6 +308,14 @@ class CaviBatch:
         _check(lib().cavi_batch_get_state(self.h, int(b), _dp(alpha), _dp(m), _dp(beta), _dp(a), _dp(bb)))
         return alpha, m, beta, a, bb
 
+    def set_state_warm(self, out, ld: int | None = None):
+        """State of every dataset from MLP output rows ``out`` (B x ld float32, device)."""
+        _check_dev(out, "out", 2)
+        if out.shape[0] < self.B:
+            raise ValueError("out has fewer rows than datasets")
+        _check(lib().cavi_batch_set_state_warm(self.h, C.c_void_p(out.data_ptr()),
+                                               int(out.shape[1] if ld is None else ld)))
+
     def sweep(self, n: int):
         _check(lib().cavi_batch_sweep(self.h, int(n)))
 
@@ -312,6 +333,116 @@ class CaviBatch:
     def close(self):
         if getattr(self, "h", None):
             _check(lib().cavi_batch_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------------- learned warm start
+FEATURES_PER_GENE = 18
+
+
+def _check_dev(t, name: str, dim: int | None = None, dtype=None):
+    import torch
+
+    dtype = torch.float32 if dtype is None else dtype
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()
+            and (dim is None or t.dim() == dim)):
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor on the GPU")
+
+
+def cavi_features(x, row_off, stream=None):
+    """Per-dataset features (B x 18G float32) of concatenated rows ``x`` cut at ``row_off``
+    (device int64, B+1 offsets)."""
+    import torch
+
+    _check_dev(x, "x", 2)
+    _check_dev(row_off, "row_off", 1, torch.int64)
+    B, G = row_off.numel() - 1, x.shape[1]
+    feat = torch.empty((B, FEATURES_PER_GENE * G), dtype=torch.float32, device=x.device)
+    _check(lib().cavi_features(C.c_void_p(x.data_ptr()), C.c_void_p(row_off.data_ptr()), B, G,
+                               C.c_void_p(feat.data_ptr()), _stream_ptr(stream)))
+    return feat
+
+
+def cavi_warm_targets(pi, mu, tau, stream=None):
+    """Training targets (B x K(2G+1) float32) from generating parameters pi (B x K), mu, tau
+    (B x K x G), float64 device tensors."""
+    import torch
+
+    _check_dev(pi, "pi", 2, torch.float64)
+    _check_dev(mu, "mu", 3, torch.float64)
+    _check_dev(tau, "tau", 3, torch.float64)
+    B, K, G = mu.shape
+    out = torch.empty((B, K * (2 * G + 1)), dtype=torch.float32, device=mu.device)
+    _check(lib().cavi_warm_targets(C.c_void_p(pi.data_ptr()), C.c_void_p(mu.data_ptr()),
+                                   C.c_void_p(tau.data_ptr()), B, K, G, C.c_void_p(out.data_ptr()),
+                                   _stream_ptr(stream)))
+    return out
+
+
+class CaviMLP:
+    """Owning wrapper of a ``cavi_mlp`` handle (in -> hidden x n_hidden (GELU) -> out)."""
+
+    def __init__(self, in_dim: int, hidden: int, n_hidden: int, out_dim: int, max_batch: int, seed: int = 0,
+                 stream=None):
+        self.dims = [int(in_dim)] + [int(hidden)] * int(n_hidden) + [int(out_dim)]
+        self.max_batch = int(max_batch)
+        h = C.c_void_p()
+        _check(lib().cavi_mlp_create(C.byref(h), int(in_dim), int(hidden), int(n_hidden), int(out_dim),
+                                     self.max_batch, C.c_uint64(seed), _stream_ptr(stream)))
+        self.h = h
+        n = C.c_int64(0)
+        _check(lib().cavi_mlp_n_params(self.h, C.byref(n)))
+        self.n_params = int(n.value)
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().cavi_mlp_get_params(self.h, out.ctypes.data))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        if p.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {p.size}")
+        _check(lib().cavi_mlp_set_params(self.h, p.ctypes.data))
+
+    def get_grads(self) -> np.ndarray:
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().cavi_mlp_get_grads(self.h, out.ctypes.data))
+        return out
+
+    def forward(self, feat):
+        import torch
+
+        _check_dev(feat, "feat", 2)
+        out = torch.empty((feat.shape[0], self.dims[-1]), dtype=torch.float32, device=feat.device)
+        _check(lib().cavi_mlp_forward(self.h, C.c_void_p(feat.data_ptr()), int(feat.shape[0]),
+                                      C.c_void_p(out.data_ptr())))
+        return out
+
+    def loss_grad(self, feat, target, want_loss: bool = True):
+        _check_dev(feat, "feat", 2)
+        _check_dev(target, "target", 2)
+        if target.shape[0] != feat.shape[0] or target.shape[1] != self.dims[-1]:
+            raise ValueError("target shape does not match the batch and the output width")
+        loss = C.c_float(0.0)
+        _check(lib().cavi_mlp_loss_grad(self.h, C.c_void_p(feat.data_ptr()), C.c_void_p(target.data_ptr()),
+                                        int(feat.shape[0]), C.byref(loss) if want_loss else None))
+        return float(loss.value) if want_loss else None
+
+    def adamw(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+              weight_decay: float = 0.0):
+        _check(lib().cavi_mlp_adamw(self.h, float(lr), float(beta1), float(beta2), float(eps),
+                                    float(weight_decay)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(lib().cavi_mlp_destroy(self.h))
             self.h = None
 
     def __del__(self):

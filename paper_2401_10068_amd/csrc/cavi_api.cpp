@@ -459,6 +459,10 @@ cavi_status run_all(Handle *h, int32_t max_sweeps, double rel_tol)
 
 }  // namespace
 
+namespace cavi {
+void set_last_error(const char *msg) { g_err = msg; }
+}  // namespace cavi
+
 struct cavi_ctx {
     Handle h;
 };
@@ -659,6 +663,21 @@ cavi_status cavi_batch_set_state(cavi_batch *bt, int32_t b, const double *alpha,
     if (!bt) return fail(CAVI_E_INVAL, "batch is NULL");
     if (b < 0 || b >= bt->h.s.B) return fail(CAVI_E_INVAL, "dataset %d outside [0, %d)", b, bt->h.s.B);
     return set_state_one(&bt->h, b, alpha, m, beta, a, bb);
+}
+
+cavi_status cavi_batch_set_state_warm(cavi_batch *bt, const float *out_dev, int32_t ld)
+{
+    if (!bt || !out_dev) return fail(CAVI_E_INVAL, "NULL argument");
+    Handle *h = &bt->h;
+    for (int i = 0; i < h->s.B; ++i) {
+        const int64_t need = (int64_t)h->ds[i].K * (2 * h->s.G + 1);
+        if (ld < need) return fail(CAVI_E_INVAL, "ld=%d < K(2G+1)=%lld (dataset %d)", ld, (long long)need, i);
+    }
+    HIPCHK(launch_warm_state(h->s, h->b, h->p, out_dev, ld, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    std::fill(h->have_state.begin(), h->have_state.end(), 1);
+    h->coef_dirty = true;
+    return CAVI_OK;
 }
 
 cavi_status cavi_batch_get_state(cavi_batch *bt, int32_t b, double *alpha, double *m, double *beta, double *a,

@@ -91,6 +91,9 @@ __device__ __forceinline__ bool sweep_skipped(const Ctl *c)
     return c->numeric || c->call_sweeps >= c->max_call || (c->stop_on_conv && c->converged);
 }
 
+// Text returned by cavi_last_error() for the calling thread.
+void set_last_error(const char *msg);
+
 // Bytes of LDS per block the device allows (set by prepare_kernels()).
 extern int g_lds_limit;
 
@@ -123,5 +126,18 @@ hipError_t launch_wsum(const Shape &s, const Bufs &b, int dataset, int e, hipStr
 // k-means++ of every dataset on the device, one workgroup per dataset.
 hipError_t launch_kmeanspp_batch(const Shape &s, const Bufs &b, const unsigned long long *seeds_dev,
                                  hipStream_t st);
+
+// Learned warm start (warmstart.hip).
+hipError_t launch_features(const float *x, const int64_t *row_off, int B, int G, float *feat, hipStream_t st);
+hipError_t launch_targets(const double *pi, const double *mu, const double *tau, int B, int K, int G, float *tgt,
+                          hipStream_t st);
+hipError_t launch_gemm(bool ta, bool tb, int M, int N, int K, const float *A, int lda, const float *B, int ldb,
+                       const float *bias, float *Z, float *Y, int ldc, int act, hipStream_t st);
+hipError_t launch_gelu_back(int n, const float *Z, const float *dY, float *dZ, hipStream_t st);
+hipError_t launch_colsum(int M, int N, const float *D, float *out, hipStream_t st);
+hipError_t launch_mse(int n, float scale, const float *Y, const float *T, float *dY, double *part, hipStream_t st);
+hipError_t launch_adamw(int64_t n, float *w, const float *g, float *m, float *v, float lr, float b1, float b2,
+                        float eps, float wd, float c1, float c2, hipStream_t st);
+hipError_t launch_warm_state(const Shape &s, const Bufs &b, const Prior &p, const float *out, int ld, hipStream_t st);
 
 }  // namespace cavi

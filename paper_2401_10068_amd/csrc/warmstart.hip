@@ -1,0 +1,376 @@
+// Learned warm start of the batched CAVI path: per-dataset features, the
+// training targets, a small MLP (hidden layers with GELU) trained and
+// evaluated with BF16 MFMA products accumulated in FP32, and the conversion of
+// its outputs into an initial variational state.
+//
+// Features of a dataset, per gene g (18 values, gene-major, 18 G in all):
+//   (mean_g - 25) / 10, ln max(var_g, 1e-30) (population variance over all N rows), and
+//   (q_gj - 25) / 10 for the 16 nearest-rank quantiles q_gj = s[floor((2j+1) M / 32)]
+//   of the first M = min(N, 4096) rows sorted ascending (s).
+// Targets of a generated dataset (K components sorted by their mean over
+// genes, ascending, ties by index): (mu - 25) / 10 [K G], ln tau [K G], ln pi [K].
+#include <math.h>
+
+#include "cavi_impl.h"
+
+namespace cavi {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kSortMax = 4096;  // rows whose quantiles are taken
+constexpr int kTM = 64, kTN = 64, kTK = 32;  // GEMM tile
+
+__device__ __forceinline__ __bf16 to_bf16(float f)
+{
+    // round to nearest even (finite inputs)
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    const unsigned short h = (unsigned short)(u >> 16);
+    return __builtin_bit_cast(__bf16, h);
+}
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+
+__device__ __forceinline__ float gelu_grad(float z)
+{
+    const float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
+    const float pdf = 0.39894228040143268f * __expf(-0.5f * z * z);
+    return cdf + z * pdf;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// features: one workgroup per (gene, dataset)
+__global__ __launch_bounds__(kBlock) void k_features(const float *__restrict__ x, const int64_t *__restrict__ row_off,
+                                                     int G, float *__restrict__ feat)
+{
+    __shared__ float sv[kSortMax];
+    __shared__ double red[kBlock];
+    const int g = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+    const int64_t r0 = row_off[b], N = row_off[b + 1] - r0;
+    const float *xc = x + r0 * G + g;
+    double s = 0.0;
+    for (int64_t n = tid; n < N; n += kBlock) s += (double)xc[n * G];
+    red[tid] = s;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (tid < off) red[tid] += red[tid + off];
+        __syncthreads();
+    }
+    const double mean = red[0] / (double)N;
+    __syncthreads();
+    s = 0.0;
+    for (int64_t n = tid; n < N; n += kBlock) {
+        const double d = (double)xc[n * G] - mean;
+        s += d * d;
+    }
+    red[tid] = s;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (tid < off) red[tid] += red[tid + off];
+        __syncthreads();
+    }
+    const double var = fmax(red[0] / (double)N, 1e-30);
+    // bitonic sort of the first M values (padded with +inf to a power of two)
+    const int M = (int)min(N, (int64_t)kSortMax);
+    int P = 1;
+    while (P < M) P <<= 1;
+    for (int i = tid; i < P; i += kBlock) sv[i] = i < M ? xc[(int64_t)i * G] : INFINITY;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < P; i += kBlock) {
+                const int p = i ^ j;
+                if (p > i) {
+                    const float a = sv[i], c = sv[p];
+                    const bool up = (i & k) == 0;
+                    if ((a > c) == up) {
+                        sv[i] = c;
+                        sv[p] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    float *f = feat + (size_t)b * 18 * G + (size_t)g * 18;
+    if (tid == 0) {
+        f[0] = (float)((mean - 25.0) / 10.0);
+        f[1] = (float)log(var);
+    }
+    if (tid < 16) {
+        const int idx = (int)(((int64_t)(2 * tid + 1) * M) / 32);
+        f[2 + tid] = (float)(((double)sv[idx] - 25.0) / 10.0);
+    }
+}
+
+// targets: one thread per dataset
+__global__ void k_targets(const double *__restrict__ pi, const double *__restrict__ mu,
+                          const double *__restrict__ tau, int B, int K, int G, float *__restrict__ tgt)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    int order[kMaxK];
+    double key[kMaxK];
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int g = 0; g < G; ++g) s += mu[((size_t)b * K + k) * G + g];
+        key[k] = s / G;
+        order[k] = k;
+    }
+    for (int i = 1; i < K; ++i) {  // insertion sort by (mean, index)
+        const int o = order[i];
+        int j = i - 1;
+        while (j >= 0 && key[order[j]] > key[o]) {
+            order[j + 1] = order[j];
+            --j;
+        }
+        order[j + 1] = o;
+    }
+    const size_t KG = (size_t)K * G;
+    float *t = tgt + (size_t)b * (2 * KG + K);
+    for (int sl = 0; sl < K; ++sl) {
+        const int k = order[sl];
+        for (int g = 0; g < G; ++g) {
+            t[(size_t)sl * G + g] = (float)((mu[((size_t)b * K + k) * G + g] - 25.0) / 10.0);
+            t[KG + (size_t)sl * G + g] = (float)log(tau[((size_t)b * K + k) * G + g]);
+        }
+        t[2 * KG + sl] = (float)log(pi[(size_t)b * K + k]);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// C[M x N] = op(A)[M x K] op(B)[K x N] (+ bias[N]); optional GELU into Y (Z keeps the
+// pre-activation).  op(A)[m][k] = TA ? A[k lda + m] : A[m lda + k];
+// op(B)[k][n] = TB ? B[n ldb + k] : B[k ldb + n].  Operands are rounded to BF16 as
+// they are staged in LDS; products accumulate in FP32 on MFMA 16x16x32.
+// 256 threads: 4 waves, each a 32 x 32 sub-tile (2 x 2 MFMA tiles).
+template <bool TA, bool TB>
+__global__ __launch_bounds__(kBlock) void k_gemm(int M, int N, int K, const float *__restrict__ A, int lda,
+                                                 const float *__restrict__ B, int ldb, const float *__restrict__ bias,
+                                                 float *__restrict__ Z, float *__restrict__ Y, int ldc, int act)
+{
+    __shared__ __bf16 As[kTM][kTK + 8];  // [m][k]
+    __shared__ __bf16 Bs[kTN][kTK + 8];  // [n][k]
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
+    const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += kTK) {
+        for (int e = tid; e < kTM * kTK; e += kBlock) {
+            int mm, kk;
+            if (TA) {
+                mm = e % kTM;
+                kk = e / kTM;
+            } else {
+                kk = e % kTK;
+                mm = e / kTK;
+            }
+            const int m = m0 + mm, k = k0 + kk;
+            float v = 0.f;
+            if (m < M && k < K) v = TA ? A[(size_t)k * lda + m] : A[(size_t)m * lda + k];
+            As[mm][kk] = to_bf16(v);
+        }
+        for (int e = tid; e < kTN * kTK; e += kBlock) {
+            int nn, kk;
+            if (TB) {
+                kk = e % kTK;
+                nn = e / kTK;
+            } else {
+                nn = e % kTN;
+                kk = e / kTN;
+            }
+            const int n = n0 + nn, k = k0 + kk;
+            float v = 0.f;
+            if (n < N && k < K) v = TB ? B[(size_t)n * ldb + k] : B[(size_t)k * ldb + n];
+            Bs[nn][kk] = to_bf16(v);
+        }
+        __syncthreads();
+        const int r = lane & 15, kq = (lane >> 4) * 8;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            bf16x8 a;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) a[t] = As[wm + 16 * i + r][kq + t];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                bf16x8 bb;
+#pragma unroll
+                for (int t = 0; t < 8; ++t) bb[t] = Bs[wn + 16 * j + r][kq + t];
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // lane holds rows 4 (lane / 16) + e, column lane % 16 of each 16 x 16 tile
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + e;
+                const int n = n0 + wn + 16 * j + (lane & 15);
+                if (m < M && n < N) {
+                    float z = acc[i][j][e] + (bias ? bias[n] : 0.f);
+                    Z[(size_t)m * ldc + n] = z;
+                    if (Y) Y[(size_t)m * ldc + n] = act ? gelu(z) : z;
+                }
+            }
+}
+
+// dZ = dY * gelu'(Z), elementwise
+__global__ void k_gelu_back(int n, const float *__restrict__ Z, const float *__restrict__ dY, float *__restrict__ dZ)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dZ[i] = dY[i] * gelu_grad(Z[i]);
+}
+
+// column sums of a M x N matrix (fixed order per column)
+__global__ void k_colsum(int M, int N, const float *__restrict__ D, float *__restrict__ out)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    double s = 0.0;
+    for (int m = 0; m < M; ++m) s += (double)D[(size_t)m * N + n];
+    out[n] = (float)s;
+}
+
+// mean squared error and its gradient dY = 2 (Y - T) / (M N); per-block FP64 partial losses
+__global__ void k_mse(int n, float scale, const float *__restrict__ Y, const float *__restrict__ T,
+                      float *__restrict__ dY, double *__restrict__ part)
+{
+    __shared__ double red[kBlock];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double l = 0.0;
+    if (i < n) {
+        const float d = Y[i] - T[i];
+        dY[i] = 2.0f * d * scale;
+        l = (double)d * (double)d;
+    }
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// AdamW on FP32 master parameters
+__global__ void k_adamw(int64_t n, float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                        float *__restrict__ v, float lr, float b1, float b2, float eps, float wd, float c1, float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / c1, vh = vi / c2;
+    w[i] -= lr * (mh / (sqrtf(vh) + eps) + wd * w[i]);
+}
+
+// MLP output rows -> variational state of each dataset of a batch (its own K):
+//   pi = softmax(log pi), alpha = alpha0 + N pi, beta = beta0 + N pi_k,
+//   m = 25 + 10 mhat, a = a0 + N pi_k / 2, b = a / exp(ln tau).
+__global__ void k_warm_state(Shape s, Bufs bf, Prior p, const float *__restrict__ out, int ld)
+{
+    const int bi = blockIdx.x, tid = threadIdx.x, G = s.G;
+    const Ds d = bf.ds[bi];
+    const int K = d.K;
+    const float *o = out + (size_t)bi * ld;
+    const size_t kb = (size_t)bi * s.Kmax, kg = kb * G;
+    __shared__ double pk[kMaxK];
+    if (tid == 0) {
+        double mx = -INFINITY;
+        for (int k = 0; k < K; ++k) mx = fmax(mx, (double)o[2 * K * G + k]);
+        double se = 0.0;
+        for (int k = 0; k < K; ++k) se += exp((double)o[2 * K * G + k] - mx);
+        for (int k = 0; k < K; ++k) pk[k] = exp((double)o[2 * K * G + k] - mx) / se;
+    }
+    __syncthreads();
+    if (tid < K) bf.alpha[kb + tid] = p.alpha0 + d.N * pk[tid];
+    for (int q = tid; q < K * G; q += kBlock) {
+        const int k = q / G;
+        const double nk = d.N * pk[k];
+        const double a = p.a0 + 0.5 * nk;
+        const double lt = fmin(fmax((double)o[K * G + q], -30.0), 30.0);
+        bf.m[kg + q] = 25.0 + 10.0 * (double)o[q];
+        bf.beta[kg + q] = p.beta0 + nk;
+        bf.a[kg + q] = a;
+        bf.b[kg + q] = a / exp(lt);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+hipError_t launch_features(const float *x, const int64_t *row_off, int B, int G, float *feat, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_features, dim3(G, B), dim3(kBlock), 0, st, x, row_off, G, feat);
+    return hipGetLastError();
+}
+
+hipError_t launch_targets(const double *pi, const double *mu, const double *tau, int B, int K, int G, float *tgt,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL(k_targets, dim3((B + 63) / 64), dim3(64), 0, st, pi, mu, tau, B, K, G, tgt);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm(bool ta, bool tb, int M, int N, int K, const float *A, int lda, const float *B, int ldb,
+                       const float *bias, float *Z, float *Y, int ldc, int act, hipStream_t st)
+{
+    const dim3 grid((N + kTN - 1) / kTN, (M + kTM - 1) / kTM);
+    if (!ta && !tb)
+        hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(kBlock), 0, st, M, N, K, A, lda, B, ldb, bias, Z, Y, ldc, act);
+    else if (!ta && tb)
+        hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(kBlock), 0, st, M, N, K, A, lda, B, ldb, bias, Z, Y, ldc, act);
+    else if (ta && !tb)
+        hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(kBlock), 0, st, M, N, K, A, lda, B, ldb, bias, Z, Y, ldc, act);
+    else
+        hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(kBlock), 0, st, M, N, K, A, lda, B, ldb, bias, Z, Y, ldc, act);
+    return hipGetLastError();
+}
+
+hipError_t launch_gelu_back(int n, const float *Z, const float *dY, float *dZ, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gelu_back, dim3((n + 255) / 256), dim3(256), 0, st, n, Z, dY, dZ);
+    return hipGetLastError();
+}
+
+hipError_t launch_colsum(int M, int N, const float *D, float *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_colsum, dim3((N + 255) / 256), dim3(256), 0, st, M, N, D, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mse(int n, float scale, const float *Y, const float *T, float *dY, double *part, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mse, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, n, scale, Y, T, dY, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_adamw(int64_t n, float *w, const float *g, float *m, float *v, float lr, float b1, float b2,
+                        float eps, float wd, float c1, float c2, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_adamw, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, w, g, m, v, lr, b1, b2, eps,
+                       wd, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_warm_state(const Shape &s, const Bufs &b, const Prior &p, const float *out, int ld, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_warm_state, dim3(s.B), dim3(kBlock), 0, st, s, b, p, out, ld);
+    return hipGetLastError();
+}
+
+}  // namespace cavi

@@ -213,9 +213,10 @@ def make_dataset(seed: int, dataset: int, N: int, recipe: Recipe, block_rows: in
     return x, z, pi, mu, tau
 
 
-def batch_shapes(seed: int, B: int, n_lo: int, n_hi: int, k_lo: int, k_hi: int):
-    """Per-dataset sizes: ``N_b = round(exp(U(ln n_lo, ln n_hi)))``, ``K_b = k_lo + floor((k_hi-k_lo+1) U)``."""
-    b = np.arange(B, dtype=np.uint64)
+def batch_shapes(seed: int, B: int, n_lo: int, n_hi: int, k_lo: int, k_hi: int, offset: int = 0):
+    """Sizes of datasets ``offset .. offset+B-1``: ``N_b = round(exp(U(ln n_lo, ln n_hi)))``,
+    ``K_b = k_lo + floor((k_hi-k_lo+1) U)``."""
+    b = np.arange(offset, offset + B, dtype=np.uint64)
     w = philox4x32_10(b & np.uint64(_MASK), b >> np.uint64(32), 0, STREAM_SHAPES, seed & _MASK, SHAPES_KEY1)
     un = u53(w[0], w[1])
     uk = u53(w[2], w[3])

@@ -1,0 +1,242 @@
+"""Learned warm start through the C ABI against the FP64 oracle
+(oracle/mlp_oracle.py): features, targets, the BF16 MFMA MLP (forward,
+gradients, AdamW, initialisation), the output -> state converter, and the
+batched CAVI run that starts from it.
+
+Tolerances.  Features: the order statistics are copies of stored values
+(exact); mean and log-variance are FP64 sums in another order, rounded to FP32
+(1 ulp).  MLP: both sides round the same FP32 operands to BF16, so the
+products are exact; the device accumulates in FP32 (relative error about
+K 2^-24 of the sum of |terms|), and an activation that lands within that error
+of a BF16 rounding boundary may round the other way (2^-8 relative of that
+operand).  Outputs and gradients are compared per tensor in the Frobenius
+norm at 3e-3 relative, plus an elementwise bound scaled to the tensor.
+"""
+import numpy as np
+import pytest
+
+from oracle import cavi_oracle as oc
+from oracle import mlp_oracle as mo
+from paper_2401_10068_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2401_10068_amd import cavi
+
+    cavi.lib()
+    return torch
+
+
+def cpu_batch(seed, Ns, K, G, dir_alpha=1.0):
+    rec = synth.Recipe(K=K, G=G, dir_alpha=dir_alpha)
+    xs, pis, mus, taus = [], [], [], []
+    for b, N in enumerate(Ns):
+        x, _, pi, mu, tau = synth.make_dataset(seed, b, int(N), rec)
+        xs.append(x)
+        pis.append(pi)
+        mus.append(mu)
+        taus.append(tau)
+    off = np.zeros(len(Ns) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(Ns)
+    return np.concatenate(xs), off, np.stack(pis), np.stack(mus), np.stack(taus)
+
+
+def close_tensor(got, want, rel=3e-3, name=""):
+    got, want = np.asarray(got, np.float64), np.asarray(want, np.float64)
+    scale = np.linalg.norm(want) + 1e-30
+    err = np.linalg.norm(got - want) / scale
+    assert err <= rel, f"{name}: relative Frobenius error {err:.3e} > {rel}"
+    bound = 0.05 * np.max(np.abs(want)) + 1e-6
+    worst = np.max(np.abs(got - want))
+    assert worst <= bound, f"{name}: max abs error {worst:.3e} > {bound:.3e}"
+
+
+# ----------------------------------------------------------------------------- features / targets
+@pytest.mark.parametrize("G", [48, 7])
+def test_features_parity(torch_cuda, G):
+    from paper_2401_10068_amd.cavi import cavi_features
+
+    Ns = [1, 5, 100, 4095, 4096, 4097, 9000]
+    x, off, *_ = cpu_batch(41, Ns, 3, G)
+    feat = cavi_features(torch_cuda.from_numpy(x).cuda(), torch_cuda.from_numpy(off).cuda()).cpu().numpy()
+    want = mo.features(x, off)
+    f, w = feat.reshape(len(Ns), G, 18), want.reshape(len(Ns), G, 18)
+    np.testing.assert_array_equal(f[:, :, 2:], w[:, :, 2:])
+    np.testing.assert_allclose(f[:, :, :2], w[:, :, :2], rtol=3e-7, atol=3e-7)
+
+
+def test_targets_parity(torch_cuda):
+    from paper_2401_10068_amd.cavi import cavi_warm_targets
+
+    _, _, pi, mu, tau = cpu_batch(42, [10] * 37, 8, 48)
+    dev = [torch_cuda.from_numpy(np.ascontiguousarray(v)).cuda() for v in (pi, mu, tau)]
+    got = cavi_warm_targets(*dev).cpu().numpy()
+    np.testing.assert_allclose(got, mo.targets(pi, mu, tau), rtol=3e-7, atol=1e-7)
+
+
+# ----------------------------------------------------------------------------- MLP
+def test_mlp_init_matches_oracle(torch_cuda):
+    from paper_2401_10068_amd.cavi import CaviMLP
+
+    net = CaviMLP(864, 256, 3, 776, 8, seed=12345)
+    dims = mo.layer_dims(864, 256, 3, 776)
+    assert net.n_params == mo.n_params(dims)
+    np.testing.assert_array_equal(net.get_params(), mo.init_params(dims, 12345))
+    net.close()
+
+
+@pytest.mark.parametrize("dims,B", [([45, 37], 70), ([40, 70, 70, 30], 130), ([8, 3, 5], 1)])
+def test_mlp_forward_and_gradients(torch_cuda, dims, B):
+    """Ragged shapes (not multiples of the 64 x 64 x 32 tiles) exercise every bound check and
+    the MFMA operand/result lane layout of all three product forms."""
+    from paper_2401_10068_amd.cavi import CaviMLP
+
+    rng = np.random.default_rng(sum(dims) + B)
+    net = CaviMLP(dims[0], dims[1] if len(dims) > 2 else 1, len(dims) - 2, dims[-1], max(B, 4), seed=1)
+    p = (rng.standard_normal(net.n_params) * 0.3).astype(np.float32)
+    net.set_params(p)
+    feat = rng.standard_normal((B, dims[0])).astype(np.float32)
+    tgt = rng.standard_normal((B, dims[-1])).astype(np.float32)
+    fd, td = torch_cuda.from_numpy(feat).cuda(), torch_cuda.from_numpy(tgt).cuda()
+    out = net.forward(fd).cpu().numpy()
+    want, _, _ = mo.forward(p, dims, feat)
+    close_tensor(out, want, 1e-3, "forward")
+    loss = net.loss_grad(fd, td)
+    wl, wg = mo.loss_grad(p, dims, feat, tgt)
+    assert loss == pytest.approx(wl, rel=2e-3)
+    g = net.get_grads()
+    o = 0
+    for l in range(len(dims) - 1):
+        nW, nb = dims[l + 1] * dims[l], dims[l + 1]
+        close_tensor(g[o:o + nW], wg[o:o + nW], 3e-3, f"dW{l}")
+        close_tensor(g[o + nW:o + nW + nb], wg[o + nW:o + nW + nb], 3e-3, f"db{l}")
+        o += nW + nb
+    net.close()
+
+
+def test_mlp_full_size_on_features(torch_cuda):
+    """The warm-start network (864 -> 256 x 3 -> 776) on features of generated datasets."""
+    from paper_2401_10068_amd.cavi import CaviMLP, cavi_features, cavi_warm_targets
+
+    Ns = np.full(96, 700)
+    x, off, pi, mu, tau = cpu_batch(43, Ns, 8, 48)
+    feat = cavi_features(torch_cuda.from_numpy(x).cuda(), torch_cuda.from_numpy(off).cuda())
+    tgt = cavi_warm_targets(*[torch_cuda.from_numpy(np.ascontiguousarray(v)).cuda() for v in (pi, mu, tau)])
+    dims = mo.layer_dims(864, 256, 3, 776)
+    net = CaviMLP(864, 256, 3, 776, 128, seed=7)
+    p = net.get_params()
+    fh, th = mo.features(x, off), mo.targets(pi, mu, tau)
+    close_tensor(net.forward(feat).cpu().numpy(), mo.forward(p, dims, fh)[0], 1e-3, "forward")
+    loss = net.loss_grad(feat, tgt)
+    wl, wg = mo.loss_grad(p, dims, fh, th)
+    assert loss == pytest.approx(wl, rel=2e-3)
+    close_tensor(net.get_grads(), wg, 3e-3, "gradient")
+    net.close()
+
+
+def test_adamw_parity(torch_cuda):
+    """Zero features make the output equal the bias exactly, so both sides' gradients are
+    determined to FP32 rounding; three AdamW steps with weight decay against the oracle."""
+    from paper_2401_10068_amd.cavi import CaviMLP
+
+    rng = np.random.default_rng(8)
+    dims, B = [3, 5], 4
+    net = CaviMLP(3, 1, 0, 5, B, seed=2)
+    p = rng.standard_normal(net.n_params).astype(np.float32)
+    net.set_params(p)
+    feat = np.zeros((B, 3), dtype=np.float32)
+    tgt = (p[15:20][None, :] + rng.choice([-1.0, 1.0], (B, 5)) * rng.uniform(0.2, 1.0, (B, 5))).astype(np.float32)
+    fd, td = torch_cuda.from_numpy(feat).cuda(), torch_cuda.from_numpy(tgt).cuda()
+    w, m, v = p.astype(np.float64), np.zeros(p.size), np.zeros(p.size)
+    for step in range(1, 4):
+        net.loss_grad(fd, td, want_loss=False)
+        net.adamw(0.05, 0.9, 0.99, 1e-8, 0.1)
+        _, g = mo.loss_grad(w.astype(np.float32), dims, feat, tgt)
+        w, m, v = mo.adamw(w, g, m, v, step, 0.05, 0.9, 0.99, 1e-8, 0.1)
+    np.testing.assert_allclose(net.get_params(), w, rtol=1e-5, atol=1e-6)
+    net.close()
+
+
+def test_training_reduces_loss(torch_cuda):
+    """Sixty AdamW steps on generated K=8, G=48 datasets lower the loss well below its start."""
+    from paper_2401_10068_amd.warmstart import WarmStart
+
+    ws = WarmStart(G=48, K=8, max_batch=64, seed=3)
+    losses = ws.train(64 * 60, batch=64, lr=1e-3, warmup=10, n_lo=200, n_hi=2000, data_seed=44)
+    assert np.all(np.isfinite(losses))
+    assert losses[-10:].mean() < 0.6 * losses[:3].mean(), losses
+    ws.close()
+
+
+# ----------------------------------------------------------------------------- warm state and CAVI
+def test_warm_state_parity(torch_cuda):
+    from paper_2401_10068_amd.cavi import CaviBatch
+
+    K, G = 8, 48
+    Ns = [300, 2048 + 5, 64, 999]
+    x, off, *_ = cpu_batch(45, Ns, K, G)
+    rng = np.random.default_rng(9)
+    out = np.concatenate([rng.normal(0, 0.6, (len(Ns), K * G)), rng.normal(1.0, 3.0, (len(Ns), K * G)),
+                          rng.normal(0, 2.0, (len(Ns), K))], axis=1).astype(np.float32)
+    out[1, K * G] = 80.0  # clamped log precision
+    bt = CaviBatch(torch_cuda.from_numpy(x).cuda(), Ns, [K] * len(Ns))
+    bt.set_state_warm(torch_cuda.from_numpy(out).cuda())
+    pr = oc.Prior()
+    for b, N in enumerate(Ns):
+        got = bt.get_state(b)
+        want = mo.warm_state(out[b], N, K, G, pr.alpha0, pr.beta0, pr.a0)
+        for gv, wv in zip(got, want):
+            np.testing.assert_allclose(gv, wv, rtol=1e-13)
+    bt.close()
+
+
+def test_warm_state_rejects_short_rows(torch_cuda):
+    from paper_2401_10068_amd.cavi import CaviBatch, CaviError
+
+    x, off, *_ = cpu_batch(46, [50, 60], 2, 4)
+    bt = CaviBatch(torch_cuda.from_numpy(x).cuda(), [50, 60], [2, 2])
+    short = torch_cuda.zeros((2, 2 * (2 * 4 + 1) - 1), device="cuda")
+    with pytest.raises(CaviError, match="E_INVAL"):
+        bt.set_state_warm(short)
+    bt.close()
+
+
+def test_warm_run_matches_oracle_and_plain(torch_cuda):
+    """Starting from the generating parameters' targets: the batched run to 1e-6 matches the
+    oracle run from the oracle's own warm state, and reaches at least the bound of the
+    standard initialisation (within 1e-6 relative) on most datasets."""
+    from paper_2401_10068_amd.cavi import CaviBatch, cavi_warm_targets
+
+    K, G = 8, 48
+    Ns = [500, 1200, 3000, 800, 2049, 650]
+    x, off, pi, mu, tau = cpu_batch(47, Ns, K, G)
+    xd = torch_cuda.from_numpy(x).cuda()
+    m0 = np.stack([oc.data_mean(x[off[b]:off[b + 1]]) for b in range(len(Ns))])
+    tgt = cavi_warm_targets(*[torch_cuda.from_numpy(np.ascontiguousarray(v)).cuda() for v in (pi, mu, tau)])
+    bt = CaviBatch(xd, Ns, [K] * len(Ns), m0=m0)
+    bt.set_state_warm(tgt)
+    sw, el, nconv = bt.run(500, 1e-6)
+    bt.close()
+    plain = CaviBatch(xd, Ns, [K] * len(Ns), m0=m0)
+    plain.init_standard(5)
+    psw, pel, _ = plain.run(500, 1e-6)
+    plain.close()
+    assert nconv == len(Ns)
+    pr = oc.Prior()
+    rows = mo.targets(pi, mu, tau)
+    accepted = 0
+    for b, N in enumerate(Ns):
+        X = x[off[b]:off[b + 1]]
+        st = oc.State(*mo.warm_state(rows[b], N, K, G, pr.alpha0, pr.beta0, pr.a0))
+        n, _, trace = oc.run(X, pr, m0[b], st, 500, 1e-6)
+        L = trace[-1]
+        assert sw[b] == n, (b, sw[b], n)
+        assert abs(el[b] - L) <= 1e-6 * abs(L), (b, el[b], L)
+        accepted += el[b] >= pel[b] - 1e-6 * abs(pel[b])
+    assert accepted >= len(Ns) - 1, (el, pel)
