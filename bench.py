@@ -135,24 +135,127 @@ def batch_bench(args) -> int:
     return 0
 
 
+def warm_bench(args) -> int:
+    """Time to ELBO convergence (1e-6 relative) of 4,096 fresh K=8 datasets: plain GPU CAVI one
+    dataset at a time (sample), batched from the standard initialisation, and batched from the
+    learned warm start (features + MLP inference + state conversion inside the timed region).
+    The MLP is trained first on generated datasets (reported separately), or loaded."""
+    import numpy as np
+    import torch
+
+    from paper_2401_10068_amd import synth
+    from paper_2401_10068_amd.cavi import Cavi, CaviBatch
+    from paper_2401_10068_amd.warmstart import WarmStart
+
+    Ns, Ks, rec, seed = synth.batch_workload("c5eval")
+    G, K = rec.G, int(Ks[0])
+    ws = WarmStart(G=G, K=K, max_batch=1024, seed=args.mlp_seed)
+    train = None
+    if args.mlp_params:
+        ws.load(args.mlp_params)
+    else:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses = ws.train(args.train_datasets, batch=1024, lr=args.lr,
+                          log_every=max(1, args.train_datasets // 1024 // 10),
+                          log=lambda m: print(m, file=sys.stderr, flush=True))
+        torch.cuda.synchronize()
+        train = {"datasets": args.train_datasets, "steps": int(losses.size), "batch": 1024,
+                 "seconds": time.perf_counter() - t0, "loss_first": float(losses[0]),
+                 "loss_last_avg10": float(losses[-10:].mean())}
+        if args.save_mlp:
+            ws.save(args.save_mlp)
+    x, row_off, _, _, _, _, _ = synth.make_batch_gpu(seed, Ns, Ks, rec)
+    off_d = row_off.to(x.device)
+    torch.cuda.synchronize()
+
+    def batched(warm: bool):
+        bt = CaviBatch(x, Ns, Ks)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if warm:
+            ws.warm_start(bt, x, off_d)
+        else:
+            bt.init_standard(seed)
+        torch.cuda.synchronize()
+        t_init = time.perf_counter() - t0
+        sw, el, nconv = bt.run(args.max_sweeps, 1e-6)
+        torch.cuda.synchronize()
+        t_all = time.perf_counter() - t0
+        bt.close()
+        return {"init_s": t_init, "total_s": t_all, "converged": nconv, "sweeps_total": int(sw.sum()),
+                "sweeps_median": float(np.median(sw)), "sweeps_p90": float(np.percentile(sw, 90)),
+                "sweeps_max": int(sw.max())}, sw, el
+
+    plain_b, psw, pel = batched(False)
+    warm_b, wsw, wel = batched(True)
+    tol = 1e-6 * np.abs(pel)
+    accepted = wel >= pel - tol
+    better = wel > pel + tol
+    idx = np.arange(0, Ns.size, max(1, Ns.size // args.plain_sample))
+    t_plain = 0.0
+    for b in idx:
+        xb = x[int(row_off[b]):int(row_off[b + 1])]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cx = Cavi(xb, K)
+        cx.init_standard(seed + int(b))
+        cx.run(args.max_sweeps, 1e-6)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t0
+        cx.close()
+    frac = float(Ns[idx].sum() / Ns.sum())
+    nkg = float((wsw.astype(np.float64) * Ns * K * G).sum())
+    out = {
+        "metric": METRIC,
+        "value": nkg / warm_b["total_s"],
+        "unit": "N*K*G elems/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "data": "synthetic",
+        "dtype": "f32 (MLP: bf16 products, f32 accumulate)",
+        "config": {"workload": f"{Ns.size} fresh datasets (c5eval): N log-uniform in [{Ns.min()}, {Ns.max()}], "
+                               f"K={K}, G={G}, seed {seed}, run to 1e-6"},
+        "training": train,
+        "plain_one_at_a_time": {"sample": int(idx.size), "sample_s": t_plain, "extrapolated_s": t_plain / frac},
+        "batched_plain": plain_b,
+        "batched_warm": warm_b,
+        "warm_acceptance": {"accepted": int(accepted.sum()), "strictly_better": int(better.sum()),
+                            "datasets": int(Ns.size),
+                            "median_rel_elbo_gap": float(np.median((wel - pel) / np.abs(pel)))},
+        "speedup_warm_vs_batched_plain": plain_b["total_s"] / warm_b["total_s"],
+        "speedup_warm_vs_plain": (t_plain / frac) / warm_b["total_s"],
+    }
+    ws.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c2", choices=["small", "c2", "c3", "c4", "c5eval"])
+    ap.add_argument("--workload", default="c2", choices=["small", "c2", "c3", "c4", "c5"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
     ap.add_argument("--max-sweeps", type=int, default=10000, help="batched workloads: sweep cap")
     ap.add_argument("--plain-sample", type=int, default=256, help="batched workloads: datasets timed one at a time")
+    ap.add_argument("--train-datasets", type=int, default=1_000_000, help="c5: generated datasets to train on")
+    ap.add_argument("--lr", type=float, default=1e-3, help="c5: peak learning rate")
+    ap.add_argument("--mlp-seed", type=int, default=0, help="c5: MLP initialisation seed")
+    ap.add_argument("--mlp-params", default=None, help="c5: load trained MLP parameters (.npy) instead of training")
+    ap.add_argument("--save-mlp", default=None, help="c5: save the trained parameters (.npy)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the sweep shards over rows with one "
               "all-reduce of the statistics per sweep, which this build does not run.", file=sys.stderr)
         return 2
     sys.path.insert(0, ROOT)
-    if args.workload in ("c4", "c5eval"):
+    if args.workload == "c4":
         return batch_bench(args)
+    if args.workload == "c5":
+        return warm_bench(args)
     import torch
 
     from paper_2401_10068_amd import synth

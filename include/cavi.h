@@ -195,12 +195,15 @@ cavi_status cavi_batch_destroy(cavi_batch *bt);
  * an MLP to a variational state (cavi_batch_set_state_warm).
  *
  * Features (cavi_features): for each dataset b (rows row_off[b] ..
- * row_off[b+1]-1 of the FP32 device array x_dev, G columns, row_off a DEVICE
- * int64 array of B+1 offsets) and gene g, 18 values at feat_dev[b*18G + g*18
- * + j]: j=0 the mean, j=1 ln max(var, 1e-30) (population variance, FP64
- * sums), j=2..17 the 16 quantiles of the first M = min(N, 4096) rows' values
- * at ranks floor((2i+1) M / 32), i = 0..15.  Mean and quantiles are stored as
- * (v - 25)/10, the log-variance as is.  Device output, FP32.
+ * row_off[b+1]-1 of the FP32 device array x_dev, G <= 512 columns, row_off a
+ * DEVICE int64 array of B+1 offsets) and gene g, 18 values at
+ * feat_dev[b*18G + g*18 + j]: j=0 the mean, j=1 ln max(var, 1e-30)
+ * (population variance, FP64 sums), j=2..17 16 rank-bin means: the first
+ * M = min(N, 4096) rows are ranked by their row sum over genes (FP64, genes
+ * in order; ties by row index), bin i holds ranks [floor(iM/16),
+ * max(floor((i+1)M/16), floor(iM/16)+1)) and its value is the mean of gene g
+ * over those rows.  Means are stored as (v - 25)/10, the log-variance as is.
+ * An empty dataset gets NaN features.  Device output, FP32.
  *
  * Targets (cavi_warm_targets): from generating parameters (DEVICE FP64:
  * pi[B*K], mu[B*K*G], tau[B*K*G], k-major per dataset) the training target

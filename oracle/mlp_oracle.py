@@ -34,9 +34,11 @@ CENTRE, SCALE = 25.0, 10.0
 
 # ----------------------------------------------------------------------------- features / targets
 def features(x, row_off) -> np.ndarray:
-    """B x 18G float32.  Per gene: (mean-25)/10, ln max(var, 1e-30) (population variance
-    over all N rows), then (q_i-25)/10 for the 16 order statistics s[floor((2i+1) M / 32)]
-    of the first M = min(N, 4096) rows sorted ascending."""
+    """B x 18G float32.  Per gene: (mean-25)/10 and ln max(var, 1e-30) (population variance
+    over all N rows), then (c_j-25)/10 for 16 rank-bin means c_j: the first M = min(N, 4096)
+    rows are ranked by their row sum (FP64, genes added in order; ties by row index); bin j
+    holds ranks floor(j M / 16) .. max(floor((j+1) M / 16), floor(j M / 16) + 1) - 1, and c_j
+    is the gene's FP64 mean over the bin's rows, summed in rank order."""
     x = np.asarray(x, dtype=np.float32)
     row_off = np.asarray(row_off, dtype=np.int64)
     B, G = row_off.size - 1, x.shape[1]
@@ -44,17 +46,26 @@ def features(x, row_off) -> np.ndarray:
     for b in range(B):
         rows = x[row_off[b]:row_off[b + 1]].astype(np.float64)
         N = rows.shape[0]
+        f = out[b].reshape(G, FEAT_PER_GENE)
+        if N == 0:
+            f[:] = np.nan
+            continue
+        mean = rows.sum(axis=0) / N
+        var = ((rows - mean) ** 2).sum(axis=0) / N
+        f[:, 0] = (mean - CENTRE) / SCALE
+        f[:, 1] = np.log(np.maximum(var, 1e-30))
         M = min(N, SORT_MAX)
+        key = np.zeros(M)
         for g in range(G):
-            col = rows[:, g]
-            mean = col.sum() / N
-            var = ((col - mean) ** 2).sum() / N
-            s = np.sort(col[:M])
-            f = out[b, g * FEAT_PER_GENE:(g + 1) * FEAT_PER_GENE]
-            f[0] = (mean - CENTRE) / SCALE
-            f[1] = math.log(max(var, 1e-30))
-            for i in range(16):
-                f[2 + i] = (s[((2 * i + 1) * M) // 32] - CENTRE) / SCALE
+            key = key + rows[:M, g]
+        rank = np.lexsort((np.arange(M), key))
+        for j in range(16):
+            lo = (j * M) // 16
+            hi = max(((j + 1) * M) // 16, lo + 1)
+            s = np.zeros(G)
+            for r in rank[lo:hi]:
+                s = s + rows[r]
+            f[:, 2 + j] = (s / (hi - lo) - CENTRE) / SCALE
     return out
 
 

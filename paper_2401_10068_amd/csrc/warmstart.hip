@@ -5,8 +5,10 @@
 //
 // Features of a dataset, per gene g (18 values, gene-major, 18 G in all):
 //   (mean_g - 25) / 10, ln max(var_g, 1e-30) (population variance over all N rows), and
-//   (q_gj - 25) / 10 for the 16 nearest-rank quantiles q_gj = s[floor((2j+1) M / 32)]
-//   of the first M = min(N, 4096) rows sorted ascending (s).
+//   (c_gj - 25) / 10 for 16 rank-bin means c_gj: the first M = min(N, 4096) rows are
+//   ranked by their row sum over genes (left-to-right FP64 sum; ties by row index), rank
+//   bin j holds ranks [floor(j M / 16), max(floor((j+1) M / 16), floor(j M / 16) + 1)),
+//   and c_gj is the mean of gene g over the rows of bin j (FP64, summed in rank order).
 // Targets of a generated dataset (K components sorted by their mean over
 // genes, ascending, ties by index): (mu - 25) / 10 [K G], ln tau [K G], ln pi [K].
 #include <math.h>
@@ -20,7 +22,7 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kSortMax = 4096;  // rows whose quantiles are taken
+constexpr int kSortMax = 4096;  // rows ranked for the rank-bin features
 constexpr int kTM = 64, kTN = 64, kTK = 32;  // GEMM tile
 
 __device__ __forceinline__ __bf16 to_bf16(float f)
@@ -44,67 +46,96 @@ __device__ __forceinline__ float gelu_grad(float z)
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------
-// features: one workgroup per (gene, dataset)
+// features: one workgroup per dataset
 __global__ __launch_bounds__(kBlock) void k_features(const float *__restrict__ x, const int64_t *__restrict__ row_off,
                                                      int G, float *__restrict__ feat)
 {
-    __shared__ float sv[kSortMax];
-    __shared__ double red[kBlock];
-    const int g = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+    __shared__ double key[kSortMax];
+    __shared__ int32_t rid[kSortMax];
+    __shared__ double part[2 * kBlock];
+    __shared__ double gmean[kMaxG];
+    const int b = blockIdx.x, tid = threadIdx.x;
     const int64_t r0 = row_off[b], N = row_off[b + 1] - r0;
-    const float *xc = x + r0 * G + g;
-    double s = 0.0;
-    for (int64_t n = tid; n < N; n += kBlock) s += (double)xc[n * G];
-    red[tid] = s;
-    __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
-        if (tid < off) red[tid] += red[tid + off];
-        __syncthreads();
+    const float *xd = x + r0 * G;
+    float *f = feat + (size_t)b * 18 * G;
+    if (N <= 0) {  // empty dataset: no features (NaN)
+        for (int q = tid; q < 18 * G; q += kBlock) f[q] = NAN;
+        return;
     }
-    const double mean = red[0] / (double)N;
-    __syncthreads();
-    s = 0.0;
-    for (int64_t n = tid; n < N; n += kBlock) {
-        const double d = (double)xc[n * G] - mean;
-        s += d * d;
+    // moments over all rows: lane slots (gene, row phase), RP rows per pass, coalesced along rows
+    const int RP = G >= kBlock ? 1 : kBlock / G;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int g0 = 0; g0 < G; g0 += kBlock) {
+            const int slots = G >= kBlock ? min(kBlock, G - g0) : RP * G;
+            double s = 0.0;
+            if (tid < slots) {
+                const int g = G >= kBlock ? g0 + tid : tid % G;
+                const int rp = G >= kBlock ? 0 : tid / G;
+                const double mu = pass ? gmean[g] : 0.0;
+                for (int64_t n = rp; n < N; n += RP) {
+                    const double v = (double)xd[n * G + g];
+                    s += pass ? (v - mu) * (v - mu) : v;
+                }
+            }
+            part[tid] = s;
+            __syncthreads();
+            const int ng = G >= kBlock ? slots : G;
+            for (int q = tid; q < ng; q += kBlock) {
+                double t = 0.0;
+                for (int r = 0; r < (G >= kBlock ? 1 : RP); ++r) t += part[r * G + q];
+                const int g = (G >= kBlock ? g0 : 0) + q;
+                if (pass == 0) {
+                    gmean[g] = t / (double)N;
+                    f[(size_t)g * 18] = (float)((t / (double)N - 25.0) / 10.0);
+                } else {
+                    f[(size_t)g * 18 + 1] = (float)log(fmax(t / (double)N, 1e-30));
+                }
+            }
+            __syncthreads();
+            if (G < kBlock) break;
+        }
     }
-    red[tid] = s;
-    __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
-        if (tid < off) red[tid] += red[tid + off];
-        __syncthreads();
-    }
-    const double var = fmax(red[0] / (double)N, 1e-30);
-    // bitonic sort of the first M values (padded with +inf to a power of two)
+    // rank the first M rows by their row sum (bitonic sort of (key, row) pairs, +inf padding)
     const int M = (int)min(N, (int64_t)kSortMax);
     int P = 1;
     while (P < M) P <<= 1;
-    for (int i = tid; i < P; i += kBlock) sv[i] = i < M ? xc[(int64_t)i * G] : INFINITY;
+    for (int i = tid; i < P; i += kBlock) {
+        double s = INFINITY;
+        if (i < M) {
+            s = 0.0;
+            for (int g = 0; g < G; ++g) s += (double)xd[(size_t)i * G + g];
+        }
+        key[i] = s;
+        rid[i] = i;
+    }
     __syncthreads();
     for (int k = 2; k <= P; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
             for (int i = tid; i < P; i += kBlock) {
                 const int p = i ^ j;
                 if (p > i) {
-                    const float a = sv[i], c = sv[p];
-                    const bool up = (i & k) == 0;
-                    if ((a > c) == up) {
-                        sv[i] = c;
-                        sv[p] = a;
+                    const double ka = key[i], kc = key[p];
+                    const int ia = rid[i], ic = rid[p];
+                    const bool gt = ka > kc || (ka == kc && ia > ic);
+                    if (gt == ((i & k) == 0)) {
+                        key[i] = kc;
+                        key[p] = ka;
+                        rid[i] = ic;
+                        rid[p] = ia;
                     }
                 }
             }
             __syncthreads();
         }
     }
-    float *f = feat + (size_t)b * 18 * G + (size_t)g * 18;
-    if (tid == 0) {
-        f[0] = (float)((mean - 25.0) / 10.0);
-        f[1] = (float)log(var);
-    }
-    if (tid < 16) {
-        const int idx = (int)(((int64_t)(2 * tid + 1) * M) / 32);
-        f[2 + tid] = (float)(((double)sv[idx] - 25.0) / 10.0);
+    // rank-bin means of every gene, summed in rank order
+    for (int q = tid; q < 16 * G; q += kBlock) {
+        const int g = q % G, j = q / G;
+        const int lo = (int)(((int64_t)j * M) / 16);
+        const int hi = max((int)(((int64_t)(j + 1) * M) / 16), lo + 1);
+        double s = 0.0;
+        for (int r = lo; r < hi; ++r) s += (double)xd[(size_t)rid[r] * G + g];
+        f[(size_t)g * 18 + 2 + j] = (float)((s / (double)(hi - lo) - 25.0) / 10.0);
     }
 }
 
@@ -315,7 +346,7 @@ __global__ void k_warm_state(Shape s, Bufs bf, Prior p, const float *__restrict_
 // ---------------------------------------------------------------------------------------------
 hipError_t launch_features(const float *x, const int64_t *row_off, int B, int G, float *feat, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_features, dim3(G, B), dim3(kBlock), 0, st, x, row_off, G, feat);
+    hipLaunchKernelGGL(k_features, dim3(B), dim3(kBlock), 0, st, x, row_off, G, feat);
     return hipGetLastError();
 }
 

@@ -65,7 +65,7 @@ cavi_status cavi_features(const float *x_dev, const int64_t *row_off_dev, int32_
                           void *hip_stream)
 {
     if (!x_dev || !row_off_dev || !feat_dev) return wfail(CAVI_E_INVAL, "NULL argument");
-    if (B < 1 || G < 1 || G > 65535) return wfail(CAVI_E_INVAL, "B=%d, G=%d out of range", B, G);
+    if (B < 1 || G < 1 || G > kMaxG) return wfail(CAVI_E_INVAL, "B=%d, G=%d out of range", B, G);
     WCHK(launch_features(x_dev, row_off_dev, B, G, feat_dev, (hipStream_t)hip_stream));
     return CAVI_OK;
 }

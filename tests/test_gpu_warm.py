@@ -3,8 +3,8 @@
 gradients, AdamW, initialisation), the output -> state converter, and the
 batched CAVI run that starts from it.
 
-Tolerances.  Features: the order statistics are copies of stored values
-(exact); mean and log-variance are FP64 sums in another order, rounded to FP32
+Tolerances.  Features: the rank-bin means are the same FP64 sums in the same
+order on both sides (exact); mean and log-variance are FP64 sums in another order, rounded to FP32
 (1 ulp).  MLP: both sides round the same FP32 operands to BF16, so the
 products are exact; the device accumulates in FP32 (relative error about
 K 2^-24 of the sum of |terms|), and an activation that lands within that error
@@ -58,15 +58,21 @@ def close_tensor(got, want, rel=3e-3, name=""):
 
 
 # ----------------------------------------------------------------------------- features / targets
-@pytest.mark.parametrize("G", [48, 7])
+@pytest.mark.parametrize("G", [48, 7, 300])
 def test_features_parity(torch_cuda, G):
+    """Rank-bin means are bitwise (same FP64 sums in the same order, same ranking); moments to
+    1 FP32 ulp.  Includes N < 16, N around the 4096-row ranking limit, and an empty dataset."""
     from paper_2401_10068_amd.cavi import cavi_features
 
-    Ns = [1, 5, 100, 4095, 4096, 4097, 9000]
+    Ns = [1, 5, 100, 4095, 4096, 4097, 9000] if G < 300 else [3, 700, 5000]
     x, off, *_ = cpu_batch(41, Ns, 3, G)
+    off = np.insert(off, 2, off[1])  # an empty dataset after the first
     feat = cavi_features(torch_cuda.from_numpy(x).cuda(), torch_cuda.from_numpy(off).cuda()).cpu().numpy()
     want = mo.features(x, off)
-    f, w = feat.reshape(len(Ns), G, 18), want.reshape(len(Ns), G, 18)
+    B = off.size - 1
+    f, w = feat.reshape(B, G, 18), want.reshape(B, G, 18)
+    assert np.all(np.isnan(f[1]))
+    f, w = np.delete(f, 1, axis=0), np.delete(w, 1, axis=0)
     np.testing.assert_array_equal(f[:, :, 2:], w[:, :, 2:])
     np.testing.assert_allclose(f[:, :, :2], w[:, :, :2], rtol=3e-7, atol=3e-7)
 

@@ -14,23 +14,40 @@ from oracle import mlp_oracle as mo
 
 
 # ----------------------------------------------------------------------------- features
-def test_features_quantiles_of_a_permutation():
-    """Rows 0..M-1 in random order: the i-th feature quantile is the order statistic of
-    rank floor((2i+1) M / 32), i.e. the value floor((2i+1) M / 32) itself."""
+def test_features_rank_bins_of_a_permutation():
+    """Rows (v, 2v, -v + 0.5 v) with v a random permutation of 0..M-1: ranking by row sum is
+    ranking by v, so bin j of gene 0 holds the integers lo..hi-1 and its mean is (lo+hi-1)/2."""
     rng = np.random.default_rng(0)
-    for M in (1, 2, 7, 32, 33, 100, 4096):
-        col = rng.permutation(M).astype(np.float32)
-        x = np.stack([col, col + 0.5], axis=1)
-        f = mo.features(x, [0, M])[0]
-        for g, shift in ((0, 0.0), (1, 0.5)):
-            q = f[g * 18 + 2:g * 18 + 18]
-            want = np.array([((2 * i + 1) * M) // 32 + shift for i in range(16)])
-            np.testing.assert_array_equal(q, ((want - 25.0) / 10.0).astype(np.float32))
+    for M in (1, 2, 7, 16, 33, 100, 4096):
+        v = rng.permutation(M).astype(np.float32)
+        x = np.stack([v, 2 * v, -0.5 * v], axis=1)
+        f = mo.features(x, [0, M])[0].reshape(3, 18)
+        for j in range(16):
+            lo = (j * M) // 16
+            hi = max(((j + 1) * M) // 16, lo + 1)
+            c = (lo + hi - 1) / 2.0
+            for g, w in enumerate((1.0, 2.0, -0.5)):
+                assert f[g, 2 + j] == np.float32((w * c - 25.0) / 10.0), (M, j, g)
 
 
-def test_features_moments_match_numpy_and_use_all_rows():
-    """Mean and population variance over all N rows (numpy's mean/var); the quantiles use only
-    the first 4096 rows, so outliers placed after them move the moments but not the quantiles."""
+def test_features_rank_bins_brute_force_with_ties():
+    """Tiny datasets against a plain-Python ranking by (row sum, row index) and bin means."""
+    rng = np.random.default_rng(10)
+    for M in (1, 3, 5, 17, 40):
+        x = rng.integers(0, 4, size=(M, 3)).astype(np.float32)  # many equal row sums
+        f = mo.features(x, [0, M])[0].reshape(3, 18)
+        order = sorted(range(M), key=lambda i: (sum(float(t) for t in x[i]), i))
+        for j in range(16):
+            lo = (j * M) // 16
+            hi = max(((j + 1) * M) // 16, lo + 1)
+            for g in range(3):
+                c = sum(float(x[order[r], g]) for r in range(lo, hi)) / (hi - lo)
+                assert f[g, 2 + j] == pytest.approx((c - 25.0) / 10.0, abs=1e-6)
+
+
+def test_features_moments_match_numpy_and_bins_use_first_rows():
+    """Mean and population variance over all N rows (numpy's mean/var); the rank bins use only
+    the first 4096 rows, so outliers placed after them move the moments but not the bins."""
     rng = np.random.default_rng(1)
     N = 5000
     x = rng.normal(25.0, 2.0, size=(N, 3)).astype(np.float32)
@@ -45,15 +62,17 @@ def test_features_moments_match_numpy_and_use_all_rows():
     assert np.all(g[:, 0] > f[:, 0] + 9.0)
 
 
-def test_features_constant_column_and_ragged_batch():
-    """Zero variance gives ln(1e-30); datasets of a batch do not see each other's rows."""
+def test_features_constant_column_ragged_batch_and_empty():
+    """Zero variance gives ln(1e-30); datasets of a batch do not see each other's rows; an
+    empty dataset has NaN features."""
     x = np.full((10, 2), 25.0, dtype=np.float32)
     x[5:] = 35.0
-    f = mo.features(x, [0, 5, 10])
+    f = mo.features(x, [0, 5, 10, 10])
     assert f[0, 0] == 0.0 and f[1, 0] == np.float32(1.0)
     assert f[0, 1] == np.float32(math.log(1e-30))
     np.testing.assert_array_equal(f[0, 2:18], 0.0)
     np.testing.assert_array_equal(f[1, 2:18], np.float32(1.0))
+    assert np.all(np.isnan(f[2]))
 
 
 # ----------------------------------------------------------------------------- targets / warm state
