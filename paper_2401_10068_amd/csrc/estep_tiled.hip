@@ -26,7 +26,9 @@
 //      nonzero r (d = x - m_kg).
 // Each wave sums its rows of a chunk in FP32 (around the previous mean, so
 // without cancellation); the four wave sums are promoted to FP64 and added in
-// wave order; the chunk partial is written as T0 | T1 | T2 | H.
+// wave order; the chunk partial is written as T0 | T1 | T2 | H.  The chunk's
+// first tile is requested before its coefficients are read, and the next tile
+// is requested as soon as the current one is in LDS.
 #include <math.h>
 
 #include "cavi_impl.h"
@@ -52,7 +54,8 @@ struct Cfg {
     static constexpr int LDS_BYTES = (kT * XS + kT * LS + KT * PS + KT) * 4;
     static_assert(G % 4 == 0 && HG % 4 == 0, "gene blocks of 4");
     static_assert((kT * G / 4) % kBlock == 0, "tile must split evenly into 16-byte loads");
-    static_assert((KT + 2 * KT * G) * 8 <= kT * XS * 4, "chunk combine must fit the x tile");
+    static_assert(8 * KT * G <= kT * XS, "per-wave sums must fit the x tile");
+    static_assert(2 * (4 * KT + 4) <= kT * LS, "per-wave counts must fit the l area");
 };
 
 template <int G>
@@ -127,7 +130,6 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
     float *ls = xs + kT * XS;         // kT x LS   partial, then exact, row log-likelihood sums
     float *pt = ls + kT * LS;         // KT x PS   (h, q) table
     float *ccs = pt + KT * PS;        // KT        c_k
-    __shared__ double red[kBlock];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -139,6 +141,12 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
         const Ds d = bf.ds[bi];
         if (sweep_skipped(bf.ctl + bi)) continue;
         const int K = d.K, KG = K * G;
+        // the chunk's first tile is requested before anything else is read
+        const int64_t r0 = d.row0 + (int64_t)(chunk - d.chunk0) * kChunkRows;
+        const int nrc = (int)min((int64_t)kChunkRows, (int64_t)d.N - (int64_t)(chunk - d.chunk0) * kChunkRows);
+        const int ntiles = (nrc + kT - 1) / kT;
+        f4 pre[C::LOADS];
+        load_tile<G>(pre, x, r0, min(kT, nrc), tid);
         const size_t kb = (size_t)bi * s.Kmax;
         const float *__restrict__ cc = bf.cc + kb;
         const float *__restrict__ hq = bf.hq + 2 * kb * G;
@@ -160,10 +168,6 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
                 mfv[k][sl] = (k < K && g < G) ? mf[k * G + g] : 0.f;
             }
 
-        const int64_t r0 = d.row0 + (int64_t)(chunk - d.chunk0) * kChunkRows;
-        const int nrc = (int)min((int64_t)kChunkRows, (int64_t)d.N - (int64_t)(chunk - d.chunk0) * kChunkRows);
-        const int ntiles = (nrc + kT - 1) / kT;
-
         float t0[KT], t1[KT][GS], t2[KT][GS];
 #pragma unroll
         for (int k = 0; k < KT; ++k) {
@@ -173,13 +177,11 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
         }
         double hacc = 0.0;
 
-        f4 pre[C::LOADS];
-        load_tile<G>(pre, x, r0, min(kT, nrc), tid);
         for (int t = 0; t < ntiles; ++t) {
             const int nr = min(kT, nrc - t * kT);
             store_tile<G>(pre, xs, nr, tid);
-            lds_barrier();
             if (t + 1 < ntiles) load_tile<G>(pre, x, r0 + (int64_t)(t + 1) * kT, min(kT, nrc - (t + 1) * kT), tid);
+            lds_barrier();
 
             // A. screen: partial sums over the first GB genes, rows lane and lane+64
             {
@@ -366,40 +368,42 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
             lds_barrier();
         }
 
-        // combine the four waves in wave order (FP64, in the LDS of the x tile)
-        double *cb = (double *)smem;
-        double c0[KT];
+        // combine the four waves in wave order: every wave leaves its FP32 sums in the LDS of
+        // the x tile (and its FP64 count and entropy sums in the l area); each chunk statistic
+        // is then ((w0 + w1) + w2) + w3 in FP64
+        float *ws = xs;              // 4 x 2KG
+        double *wd = (double *)ls;   // 4 x KT counts, then 4 entropies
 #pragma unroll
-        for (int k = 0; k < KT; ++k) c0[k] = wave_sum((double)t0[k]);
-        for (int ww = 0; ww < 4; ++ww) {
-            if (w == ww) {
+        for (int k = 0; k < KT; ++k) {
+            const double c0 = wave_sum((double)t0[k]);
+            if (k < K) {
+                if (lane == 0) wd[w * KT + k] = c0;
 #pragma unroll
-                for (int k = 0; k < KT; ++k) {
-                    if (k < K) {
-                        if (lane == 0) cb[k] = (ww == 0) ? c0[k] : cb[k] + c0[k];
-#pragma unroll
-                        for (int sl = 0; sl < GS; ++sl) {
-                            const int g = lane + 64 * sl;
-                            if (g < G) {
-                                const int i1 = K + k * G + g, i2 = K + KG + k * G + g;
-                                cb[i1] = (ww == 0) ? (double)t1[k][sl] : cb[i1] + (double)t1[k][sl];
-                                cb[i2] = (ww == 0) ? (double)t2[k][sl] : cb[i2] + (double)t2[k][sl];
-                            }
-                        }
+                for (int sl = 0; sl < GS; ++sl) {
+                    const int g = lane + 64 * sl;
+                    if (g < G) {
+                        ws[w * 2 * KG + k * G + g] = t1[k][sl];
+                        ws[w * 2 * KG + KG + k * G + g] = t2[k][sl];
                     }
                 }
             }
-            lds_barrier();
         }
-        red[tid] = hacc;
+        const double hw = wave_sum(hacc);
+        if (lane == 0) wd[4 * KT + w] = hw;
         lds_barrier();
-        for (int off = kBlock / 2; off > 0; off >>= 1) {
-            if (tid < off) red[tid] += red[tid + off];
-            lds_barrier();
-        }
         double *out = partials + (size_t)chunk * s.Smax;
-        for (int i = tid; i < K + 2 * KG; i += kBlock) out[i] = cb[i];
-        if (tid == 0) out[K + 2 * KG] = red[0];
+        for (int i = tid; i < K + 2 * KG + 1; i += kBlock) {
+            double v;
+            if (i < K) {
+                v = ((wd[i] + wd[KT + i]) + wd[2 * KT + i]) + wd[3 * KT + i];
+            } else if (i < K + 2 * KG) {
+                const int j = i - K;
+                v = (((double)ws[j] + (double)ws[2 * KG + j]) + (double)ws[4 * KG + j]) + (double)ws[6 * KG + j];
+            } else {
+                v = ((wd[4 * KT] + wd[4 * KT + 1]) + wd[4 * KT + 2]) + wd[4 * KT + 3];
+            }
+            out[i] = v;
+        }
         lds_barrier();
     }
 }
