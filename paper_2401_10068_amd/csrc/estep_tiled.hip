@@ -12,7 +12,7 @@
 //      rows; over the first GB = min(G, 16) genes it forms the partial sums
 //      P_nk.  Every term is non-negative, so U_nk = c_k - P_nk bounds l_nk
 //      from above (also in FP32: adding non-negative terms never lowers a
-//      rounded sum).  Coefficients are wave-uniform: scalar loads.
+//      rounded sum).  Coefficients are wave-uniform LDS broadcasts.
 //   B. Exact terms.  Wave w owns rows 32w..32w+31, two lanes per row (each
 //      sums half of the remaining genes with per-lane coefficients read from
 //      an LDS table).  First the subpopulation with the largest bound, then
@@ -39,6 +39,9 @@ namespace {
 
 constexpr int kT = 128;  // rows per tile
 constexpr uint32_t kOneHot = 1u << 31;
+// s_waitcnt immediate for vmcnt(0) with the other counters left alone (gfx9 encoding:
+// vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt_hi[15:14])
+constexpr int kWaitVm0 = 0x0F70;
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 template <int KT, int G>
@@ -68,7 +71,10 @@ __device__ __forceinline__ void load_tile(f4 (&pre)[(kT * G / 4) / kBlock], cons
         const int i = tid + j * kBlock;
         const int row = i / C4;
         const int col = (i - row * C4) * 4;
-        if (row < nr) pre[j] = *(const f4 *)(x + (row0 + row) * G + col);
+        // rows past the end of a ragged tile re-read the tile's last row: the loads stay
+        // unconditional, so the compiler keeps all of them in flight at once
+        const int rr = row < nr ? row : nr - 1;
+        pre[j] = *(const f4 *)(x + (row0 + rr) * G + col);
     }
 }
 
@@ -153,20 +159,38 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
         const float *__restrict__ mf = bf.mf + kb * G;
         double *__restrict__ partials = bf.partials;
 
-        for (int i = tid; i < KT * G; i += kBlock) {
-            const int k = i / G, g = i - k * G;
-            pt[k * PS + 2 * g] = k < K ? hq[2 * i] : 0.f;
-            pt[k * PS + 2 * g + 1] = k < K ? hq[2 * i + 1] : 0.f;
+        // coefficients: every load unconditional (indexes clamped into the dataset's arrays),
+        // then one wait, so that no load of the tile loop's prefetch is ever waited on early
+        constexpr int NPT = (KT * G + kBlock - 1) / kBlock;
+        float hv[NPT], qv[NPT];
+#pragma unroll
+        for (int u = 0; u < NPT; ++u) {
+            const int ic = min(tid + u * kBlock, KG - 1);
+            hv[u] = hq[2 * ic];
+            qv[u] = hq[2 * ic + 1];
         }
-        if (tid < KT) ccs[tid] = tid < K ? cc[tid] : 0.f;
+        const float ccv = cc[min(tid, K - 1)];
         float mfv[KT][GS];
 #pragma unroll
         for (int k = 0; k < KT; ++k)
 #pragma unroll
-            for (int sl = 0; sl < GS; ++sl) {
-                const int g = lane + 64 * sl;
-                mfv[k][sl] = (k < K && g < G) ? mf[k * G + g] : 0.f;
+            for (int sl = 0; sl < GS; ++sl) mfv[k][sl] = mf[min(k, K - 1) * G + min(lane + 64 * sl, G - 1)];
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+#pragma unroll
+        for (int u = 0; u < NPT; ++u) {
+            const int i = tid + u * kBlock;
+            if (i < KT * G) {
+                const int k = i / G, g = i - k * G;
+                pt[k * PS + 2 * g] = k < K ? hv[u] : 0.f;
+                pt[k * PS + 2 * g + 1] = k < K ? qv[u] : 0.f;
             }
+        }
+        if (tid < KT) ccs[tid] = tid < K ? ccv : 0.f;
+#pragma unroll
+        for (int k = 0; k < KT; ++k)
+#pragma unroll
+            for (int sl = 0; sl < GS; ++sl)
+                if (k >= K || lane + 64 * sl >= G) mfv[k][sl] = 0.f;
 
         float t0[KT], t1[KT][GS], t2[KT][GS];
 #pragma unroll
@@ -198,7 +222,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
                     for (int i = 0; i < KQ; ++i) {
                         const int k = w + 4 * i;
                         if (k < K) {
-                            const float *p = hq + 2 * (k * G + gb);
+                            // from the LDS table (a global read here would make the wave
+                            // wait for the next tile's loads as well)
+                            const float *p = pt + k * PS + 2 * gb;
                             const float h0 = p[0], q0 = p[1], h1 = p[2], q1 = p[3];
                             const float h2 = p[4], q2 = p[5], h3 = p[6], q3 = p[7];
                             float u;
