@@ -20,8 +20,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "CAVI sweeps/s (N·K·G elems/s, %HBM peak); time-to-ELBO-conv plain vs batched+warm"
 HBM_PEAK_GBS = 8000.0
-DOMINANT_KERNEL = "k_estep_stats"
-KERNEL_SRC = os.path.join(ROOT, "paper_2401_10068_amd", "csrc", "cavi_kernels.hip")
+DOMINANT_KERNEL = "k_estep_tiled"
+KERNEL_SRC = os.path.join(ROOT, "paper_2401_10068_amd", "csrc", "estep_tiled.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -239,6 +239,9 @@ def main() -> int:
     ap.add_argument("--workload", default="c2", choices=["small", "c2", "c3", "c4", "c5"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="after the bench, copy a 384,000,000-byte tensor 3 times (reference kernel of known "
+                         "traffic for hardware byte counters)")
     ap.add_argument("--max-sweeps", type=int, default=10000, help="batched workloads: sweep cap")
     ap.add_argument("--plain-sample", type=int, default=256, help="batched workloads: datasets timed one at a time")
     ap.add_argument("--train-datasets", type=int, default=1_000_000, help="c5: generated datasets to train on")
@@ -312,6 +315,13 @@ def main() -> int:
         },
     }
     cx.close()
+    if args.copy_ref:
+        src = torch.empty(96_000_000, dtype=torch.float32, device=x.device)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu:
         xh = x.cpu().numpy()
         del x

@@ -301,23 +301,50 @@ __global__ __launch_bounds__(kBlock) void k_colmean(Shape s, Bufs bf)
 // weights floor(minD2 * 2^e).
 __global__ __launch_bounds__(kBlock) void k_d2(Shape s, Bufs bf, int bi, int seed_index, int first)
 {
+    // thread t owns row blockIdx.x * 256 + t; the rows are staged through LDS 32 genes at a
+    // time (coalesced loads), and each thread adds its row's squared differences in gene
+    // order, exactly as sqdist64 does
+    constexpr int kSlab = 32;
+    __shared__ float xs[kBlock][kSlab + 1];
+    __shared__ float sd[kSlab];
     __shared__ double red[kBlock];
     const Ds d = bf.ds[bi];
-    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const float *seed = bf.seeds + ((size_t)bi * s.Kmax + seed_index) * s.G;
-    double v = 0.0;
-    if (n < d.N) {
-        const double d2 = sqdist64(bf.x + (d.row0 + n) * s.G, seed, s.G);
-        v = first ? d2 : fmin(bf.mind2[n], d2);
-        bf.mind2[n] = v;
-    }
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    const int G = s.G, tid = threadIdx.x;
+    const int64_t n0 = (int64_t)blockIdx.x * kBlock;
+    const int nr = (int)max((int64_t)0, min((int64_t)kBlock, (int64_t)d.N - n0));
+    const float *seed = bf.seeds + ((size_t)bi * s.Kmax + seed_index) * G;
+    const float *xb = bf.x + (d.row0 + n0) * G;
+    double acc = 0.0;
+    for (int g0 = 0; g0 < G; g0 += kSlab) {
+        const int w = min(kSlab, G - g0);
+        for (int e = tid; e < kBlock * kSlab; e += kBlock) {
+            const int r = e / kSlab, c = e - r * kSlab;
+            if (r < nr && c < w) xs[r][c] = xb[(int64_t)r * G + g0 + c];
+        }
+        if (tid < w) sd[tid] = seed[g0 + tid];
+        __syncthreads();
+        if (tid < nr) {
+#pragma clang fp contract(off)
+            for (int c = 0; c < w; ++c) {
+                const double dd = (double)xs[tid][c] - (double)sd[c];
+                acc = acc + dd * dd;
+            }
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) bf.blockmax[blockIdx.x] = red[0];
+    double v = 0.0;
+    if (tid < nr) {
+        const int64_t n = n0 + tid;
+        v = first ? acc : fmin(bf.mind2[n], acc);
+        bf.mind2[n] = v;
+    }
+    red[tid] = v;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (tid < off) red[tid] = fmax(red[tid], red[tid + off]);
+        __syncthreads();
+    }
+    if (tid == 0) bf.blockmax[blockIdx.x] = red[0];
 }
 
 __global__ __launch_bounds__(kBlock) void k_wsum(Shape s, Bufs bf, int bi, int e)

@@ -14,6 +14,7 @@ namespace {
 constexpr double kLn2Pi = 1.8378770664093454835606594728112;
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr int kRedBlock = 1024;  // k_reduce: 16 waves per 64 statistics
+constexpr int kMBlock = 1024;    // k_mstep, k_coef: one (k, g) item per thread up to K G = 1024
 
 // Sum over the 64 lanes of a wave with a fixed butterfly (same order every run).
 __device__ __forceinline__ double wave_sum(double v)
@@ -24,7 +25,7 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 struct MShared {
-    double red[kBlock];
+    double red[kMBlock];
     double ak[kMaxK], psi_ak[kMaxK], lg_ak[kMaxK], term_k[kMaxK];
     double tmp[kMaxKG];
     double asum, psum;
@@ -82,12 +83,12 @@ __device__ __forceinline__ double coef_item(const View &v, int q, double mm, dou
     return 0.5 * (elt - kLn2Pi - 1.0 / bt);
 }
 
-// c_k from the per-(k,g) parts in LDS: wave w sums subpopulations w, w+4, ...
+// c_k from the per-(k,g) parts in LDS: wave w sums subpopulations w, w+16, ...
 __device__ __forceinline__ void coef_rows(const View &v, MShared &sh, const Prior *p, int with_bound)
 {
     const int G = v.G, K = v.K;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int k = wv; k < K; k += kBlock / 64) {
+    for (int k = wv; k < K; k += kMBlock / 64) {
         double x = 0.0;
         for (int g = lane; g < G; g += 64) x += sh.tmp[k * G + g];
         x = wave_sum(x);
@@ -145,14 +146,14 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce(Shape s, Bufs bf, int init
 }
 
 // Coefficients of the E-step from the committed state (after set_state).
-__global__ __launch_bounds__(kBlock) void k_coef(Shape s, Bufs bf)
+__global__ __launch_bounds__(kMBlock) void k_coef(Shape s, Bufs bf)
 {
     __shared__ MShared sh;
     const View v = view(s, bf, blockIdx.x);
     const int tid = threadIdx.x, K = v.K, KG = K * v.G;
     if (tid == 0) sh.bad = 0;
     if (tid < K) sh.psi_ak[tid] = dev_digamma(v.alpha[tid]);
-    for (int q = tid; q < KG; q += kBlock) {
+    for (int q = tid; q < KG; q += kMBlock) {
         const double aa = v.a[q], bb = v.b[q];
         sh.tmp[q] = coef_item(v, q, v.m[q], v.beta[q], aa, bb, dev_digamma(aa) - log(bb));
     }
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_coef(Shape s, Bufs bf)
 // then the lower bound at the new q(pi), q(mu, tau) with the entropy H of the
 // responsibilities.  A non-finite value leaves the state untouched and raises
 // ctl->numeric.
-__global__ __launch_bounds__(kBlock) void k_mstep(Shape s, Bufs bf, Prior p, int init_mode)
+__global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, int init_mode)
 {
     const View v = view(s, bf, blockIdx.x);
     Ctl *ctl = v.ctl;
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(kBlock) void k_mstep(Shape s, Bufs bf, Prior p, int
     const double prior_const = half_ln_b0 + p.a0 * log(p.b0) - dev_lgamma(p.a0);
     double acc = 0.0;
     int bad = 0;
-    for (int q = tid; q < KG; q += kBlock) {
+    for (int q = tid; q < KG; q += kMBlock) {
         const int k = q / G, g = q - k * G;
         const double Nk = T0[k];
         const double c = (double)v.mf[q];
@@ -239,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void k_mstep(Shape s, Bufs bf, Prior p, int
     coef_rows(v, sh, &p, !init_mode);
     sh.red[tid] = acc;
     __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
+    for (int off = kMBlock / 2; off > 0; off >>= 1) {
         if (tid < off) sh.red[tid] += sh.red[tid + off];
         __syncthreads();
     }
@@ -275,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_mstep(Shape s, Bufs bf, Prior p, int
     __syncthreads();
     if (sh.bad) return;
     if (tid < K) v.alpha[tid] = v.nalpha[tid];
-    for (int q = tid; q < KG; q += kBlock) {
+    for (int q = tid; q < KG; q += kMBlock) {
         v.m[q] = v.nm[q];
         v.beta[q] = v.nbeta[q];
         v.a[q] = v.na[q];
@@ -291,13 +292,13 @@ hipError_t launch_reduce(const Shape &s, const Bufs &b, int init_mode, hipStream
 
 hipError_t launch_mstep(const Shape &s, const Bufs &b, const Prior &p, int init_mode, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mstep, dim3(s.B), dim3(kBlock), 0, st, s, b, p, init_mode);
+    hipLaunchKernelGGL(k_mstep, dim3(s.B), dim3(kMBlock), 0, st, s, b, p, init_mode);
     return hipGetLastError();
 }
 
 hipError_t launch_coef(const Shape &s, const Bufs &b, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_coef, dim3(s.B), dim3(kBlock), 0, st, s, b);
+    hipLaunchKernelGGL(k_coef, dim3(s.B), dim3(kMBlock), 0, st, s, b);
     return hipGetLastError();
 }
 
