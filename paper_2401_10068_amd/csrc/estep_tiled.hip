@@ -5,21 +5,22 @@
 // around the FP32 centre m_kg), organised for gfx950 and for the sparsity of
 // the responsibilities.
 //
-// Per 2048-row chunk (the unit of the deterministic reduction), 128-row tiles
-// are staged in LDS (row stride G+4 floats; the next tile is prefetched into
-// registers while the current one is processed).  Per tile:
-//   A. Screen.  Wave w owns subpopulations w, w+4, ...; each lane owns two
-//      rows; over the first GB = min(G, 16) genes it forms the partial sums
-//      P_nk.  Every term is non-negative, so U_nk = c_k - P_nk bounds l_nk
-//      from above (also in FP32: adding non-negative terms never lowers a
-//      rounded sum).  Coefficients are wave-uniform LDS broadcasts.
-//   B. Exact terms.  Wave w owns rows 32w..32w+31, two lanes per row (each
-//      sums half of the remaining genes with per-lane coefficients read from
-//      an LDS table).  First the subpopulation with the largest bound, then
-//      every k whose bound is within 87 of that exact value.  A k outside
-//      that set has l_nk - L_n < -87, so its responsibility is zero exactly
-//      as in the dense computation.  Then log-sum-exp over the computed set:
-//      responsibilities, entropy, counts, and a bitmask of nonzero r_nk.
+// Per 2048-row chunk (the unit of the deterministic reduction), 128-row tiles;
+// wave w owns rows 32w..32w+31 of every tile and works on them alone (no
+// workgroup barrier inside the tile loop): it stages them in its slab of the
+// LDS tile (row stride G+4 floats) while the next slab is prefetched into
+// registers.  Per slab:
+//   A. Screen.  Lane (row j, half) forms, over the first GB = min(G, 16)
+//      genes, the partial sums P_nk of subpopulations half, half+2, ...  Every
+//      term is non-negative, so U_nk = c_k - P_nk bounds l_nk from above (also
+//      in FP32: adding non-negative terms never lowers a rounded sum).
+//      Coefficients are LDS broadcasts from the chunk's (h, q) table.
+//   B. Exact terms.  Two lanes per row (each sums half of the remaining genes).
+//      First the subpopulation with the largest bound, then every k whose
+//      bound is within 87 of that exact value.  A k outside that set has
+//      l_nk - L_n < -87, so its responsibility is zero exactly as in the dense
+//      computation.  Then log-sum-exp over the computed set: responsibilities,
+//      entropy, counts, and a bitmask of nonzero r_nk.
 //   C. Statistics.  The same wave walks its rows with lanes over genes; a
 //      row with one responsibility of exactly 1 (the common case) adds d and
 //      d^2 to its subpopulation's sums, other rows add r d and r d^2 for each
@@ -49,42 +50,43 @@ struct Cfg {
     static constexpr int XS = G + 4;                     // LDS row stride of the x tile
     static constexpr int LS = (KT == 4) ? 12 : KT + 4;   // LDS row stride of the partial / exact l
     static constexpr int PS = 2 * G + 4;                 // LDS row stride of the (h, q) table
-    static constexpr int KQ = KT / 4;                    // subpopulations per wave (screen)
+    static constexpr int KH = KT / 2;                    // subpopulations per lane (screen)
     static constexpr int GS = (G + 63) / 64;             // gene slots per lane (statistics)
-    static constexpr int LOADS = (kT * G / 4) / kBlock;  // 16-byte loads per thread per tile
+    static constexpr int LOADS = G / 8;                  // 16-byte loads per lane per 32-row slab
     static constexpr int GB = G < 16 ? G : 16;           // screened genes
     static constexpr int HG = (G - GB) / 2;              // remaining genes per half row
     static constexpr int LDS_BYTES = (kT * XS + kT * LS + KT * PS + KT) * 4;
     static_assert(G % 4 == 0 && HG % 4 == 0, "gene blocks of 4");
-    static_assert((kT * G / 4) % kBlock == 0, "tile must split evenly into 16-byte loads");
+    static_assert(G % 8 == 0, "a slab must split evenly into 16-byte loads");
     static_assert(8 * KT * G <= kT * XS, "per-wave sums must fit the x tile");
     static_assert(2 * (4 * KT + 4) <= kT * LS, "per-wave counts must fit the l area");
 };
 
+// One wave's 32-row slab of a tile: G/8 16-byte loads per lane, coalesced along the rows.
+// Rows past the end of a ragged slab re-read its last row: the loads stay unconditional, so
+// the compiler keeps all of them in flight at once.
 template <int G>
-__device__ __forceinline__ void load_tile(f4 (&pre)[(kT * G / 4) / kBlock], const float *__restrict__ x,
-                                          int64_t row0, int nr, int tid)
+__device__ __forceinline__ void load_slab(f4 (&pre)[G / 8], const float *__restrict__ x, int64_t row0, int nr,
+                                          int lane)
 {
     constexpr int C4 = G / 4;
 #pragma unroll
-    for (int j = 0; j < (kT * G / 4) / kBlock; ++j) {
-        const int i = tid + j * kBlock;
+    for (int j = 0; j < G / 8; ++j) {
+        const int i = lane + j * 64;
         const int row = i / C4;
         const int col = (i - row * C4) * 4;
-        // rows past the end of a ragged tile re-read the tile's last row: the loads stay
-        // unconditional, so the compiler keeps all of them in flight at once
         const int rr = row < nr ? row : nr - 1;
         pre[j] = *(const f4 *)(x + (row0 + rr) * G + col);
     }
 }
 
 template <int G>
-__device__ __forceinline__ void store_tile(const f4 (&pre)[(kT * G / 4) / kBlock], float *xs, int nr, int tid)
+__device__ __forceinline__ void store_slab(const f4 (&pre)[G / 8], float *xs, int nr, int lane)
 {
     constexpr int C4 = G / 4, XS = G + 4;
 #pragma unroll
-    for (int j = 0; j < (kT * G / 4) / kBlock; ++j) {
-        const int i = tid + j * kBlock;
+    for (int j = 0; j < G / 8; ++j) {
+        const int i = lane + j * 64;
         const int row = i / C4;
         const int col = (i - row * C4) * 4;
         if (row < nr) *(f4 *)(xs + row * XS + col) = pre[j];
@@ -117,6 +119,13 @@ __device__ __forceinline__ void lds_barrier()
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// The wave's own LDS writes are complete (its lanes exchange data through LDS).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -130,7 +139,7 @@ template <int KT, int G>
 __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
 {
     using C = Cfg<KT, G>;
-    constexpr int XS = C::XS, LS = C::LS, PS = C::PS, KQ = C::KQ, GS = C::GS, GB = C::GB, HG = C::HG;
+    constexpr int XS = C::XS, LS = C::LS, PS = C::PS, KH = C::KH, GS = C::GS, GB = C::GB, HG = C::HG;
     extern __shared__ __align__(16) float smem[];
     float *xs = smem;                 // kT x XS   x tile
     float *ls = xs + kT * XS;         // kT x LS   partial, then exact, row log-likelihood sums
@@ -151,8 +160,12 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
         const int64_t r0 = d.row0 + (int64_t)(chunk - d.chunk0) * kChunkRows;
         const int nrc = (int)min((int64_t)kChunkRows, (int64_t)d.N - (int64_t)(chunk - d.chunk0) * kChunkRows);
         const int ntiles = (nrc + kT - 1) / kT;
+        const int jbase = 32 * w;  // the wave's rows of every tile
         f4 pre[C::LOADS];
-        load_tile<G>(pre, x, r0, min(kT, nrc), tid);
+        {
+            const int nj0 = min(32, min(kT, nrc) - jbase);
+            if (nj0 > 0) load_slab<G>(pre, x, r0 + jbase, nj0, lane);
+        }
         const size_t kb = (size_t)bi * s.Kmax;
         const float *__restrict__ cc = bf.cc + kb;
         const float *__restrict__ hq = bf.hq + 2 * kb * G;
@@ -191,6 +204,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
 #pragma unroll
             for (int sl = 0; sl < GS; ++sl)
                 if (k >= K || lane + 64 * sl >= G) mfv[k][sl] = 0.f;
+        lds_barrier();  // the coefficient table is complete
 
         float t0[KT], t1[KT][GS], t2[KT][GS];
 #pragma unroll
@@ -203,58 +217,55 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
 
         for (int t = 0; t < ntiles; ++t) {
             const int nr = min(kT, nrc - t * kT);
-            store_tile<G>(pre, xs, nr, tid);
-            if (t + 1 < ntiles) load_tile<G>(pre, x, r0 + (int64_t)(t + 1) * kT, min(kT, nrc - (t + 1) * kT), tid);
-            lds_barrier();
+            const int nj = max(0, min(32, nr - jbase));
+            // each wave stages, screens, sums and accumulates its own 32 rows: no workgroup
+            // barrier inside the tile loop
+            if (nj > 0) store_slab<G>(pre, xs + jbase * XS, nj, lane);
+            if (t + 1 < ntiles) {
+                const int nj1 = min(32, min(kT, nrc - (t + 1) * kT) - jbase);
+                if (nj1 > 0) load_slab<G>(pre, x, r0 + (int64_t)(t + 1) * kT + jbase, nj1, lane);
+            }
+            wave_lds_sync();
+            if (nj == 0) continue;
+            const int j = jbase + jl;
+            const bool act = jl < nj;
 
-            // A. screen: partial sums over the first GB genes, rows lane and lane+64
+            // A. screen: partial sums over the first GB genes; lane (row j, half) takes
+            //    subpopulations half, half + 2, ...
             {
-                float acc0[KQ], acc1[KQ];
+                float acc[KH];
 #pragma unroll
-                for (int i = 0; i < KQ; ++i) acc0[i] = acc1[i] = 0.f;
-                const float *xa = xs + lane * XS;
-                const float *xb = xs + (lane + 64) * XS;
+                for (int i = 0; i < KH; ++i) acc[i] = 0.f;
+                const float *xa = xs + j * XS;
 #pragma unroll
                 for (int gb = 0; gb < GB; gb += 4) {
                     const f4 va = *(const f4 *)(xa + gb);
-                    const f4 vb = *(const f4 *)(xb + gb);
 #pragma unroll
-                    for (int i = 0; i < KQ; ++i) {
-                        const int k = w + 4 * i;
+                    for (int i = 0; i < KH; ++i) {
+                        const int k = half + 2 * i;
                         if (k < K) {
-                            // from the LDS table (a global read here would make the wave
-                            // wait for the next tile's loads as well)
                             const float *p = pt + k * PS + 2 * gb;
                             const float h0 = p[0], q0 = p[1], h1 = p[2], q1 = p[3];
                             const float h2 = p[4], q2 = p[5], h3 = p[6], q3 = p[7];
                             float u;
-                            u = fmaf(va.x, h0, q0); acc0[i] = fmaf(u, u, acc0[i]);
-                            u = fmaf(vb.x, h0, q0); acc1[i] = fmaf(u, u, acc1[i]);
-                            u = fmaf(va.y, h1, q1); acc0[i] = fmaf(u, u, acc0[i]);
-                            u = fmaf(vb.y, h1, q1); acc1[i] = fmaf(u, u, acc1[i]);
-                            u = fmaf(va.z, h2, q2); acc0[i] = fmaf(u, u, acc0[i]);
-                            u = fmaf(vb.z, h2, q2); acc1[i] = fmaf(u, u, acc1[i]);
-                            u = fmaf(va.w, h3, q3); acc0[i] = fmaf(u, u, acc0[i]);
-                            u = fmaf(vb.w, h3, q3); acc1[i] = fmaf(u, u, acc1[i]);
+                            u = fmaf(va.x, h0, q0); acc[i] = fmaf(u, u, acc[i]);
+                            u = fmaf(va.y, h1, q1); acc[i] = fmaf(u, u, acc[i]);
+                            u = fmaf(va.z, h2, q2); acc[i] = fmaf(u, u, acc[i]);
+                            u = fmaf(va.w, h3, q3); acc[i] = fmaf(u, u, acc[i]);
                         }
                     }
                 }
+                if (act) {
 #pragma unroll
-                for (int i = 0; i < KQ; ++i) {
-                    const int k = w + 4 * i;
-                    if (k < K) {
-                        ls[lane * LS + k] = acc0[i];
-                        ls[(lane + 64) * LS + k] = acc1[i];
+                    for (int i = 0; i < KH; ++i) {
+                        const int k = half + 2 * i;
+                        if (k < K) ls[j * LS + k] = acc[i];
                     }
                 }
             }
-            lds_barrier();
+            wave_lds_sync();
 
             // B. exact terms for the candidate subpopulations of row j (lanes jl, jl+32)
-            const int jbase = 32 * w;
-            const int nj = max(0, min(32, nr - jbase));
-            const int j = jbase + jl;
-            const bool act = jl < nj;
             float *lr = ls + j * LS;
             const float *xr = xs + j * XS;
             uint32_t done = 0;
@@ -391,8 +402,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
                     }
                 }
             }
-            lds_barrier();
         }
+        lds_barrier();  // every wave is done with its rows
 
         // combine the four waves in wave order: every wave leaves its FP32 sums in the LDS of
         // the x tile (and its FP64 count and entropy sums in the l area); each chunk statistic
