@@ -240,8 +240,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
     ap.add_argument("--copy-ref", action="store_true",
-                    help="after the bench, copy a 384,000,000-byte tensor 3 times (reference kernel of known "
-                         "traffic for hardware byte counters)")
+                    help="after the bench, run an elementwise kernel 3 times that reads and writes "
+                         "384,000,000 bytes (reference of known traffic for the hardware byte counters)")
     ap.add_argument("--max-sweeps", type=int, default=10000, help="batched workloads: sweep cap")
     ap.add_argument("--plain-sample", type=int, default=256, help="batched workloads: datasets timed one at a time")
     ap.add_argument("--train-datasets", type=int, default=1_000_000, help="c5: generated datasets to train on")
@@ -316,10 +316,10 @@ def main() -> int:
     }
     cx.close()
     if args.copy_ref:
-        src = torch.empty(96_000_000, dtype=torch.float32, device=x.device)
+        src = torch.ones(96_000_000, dtype=torch.float32, device=x.device)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
     if not args.no_cpu:
