@@ -43,20 +43,6 @@ cavi_status fail(cavi_status st, const char *fmt, ...)
 constexpr int kGraphSweeps = 16;  // sweeps per captured graph
 constexpr int kHistSingle = 4096; // bounds kept by a single-dataset handle
 
-// SplitMix64 (Steele, Lea and Flood 2014) and floor(u53 * n / 2^53).
-uint64_t splitmix64(uint64_t &s)
-{
-    uint64_t z = (s += 0x9E3779B97F4A7C15ULL);
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-    return z ^ (z >> 31);
-}
-
-uint64_t scaled_draw(uint64_t &s, uint64_t n)
-{
-    const uint64_t u = splitmix64(s) >> 11;
-    return (uint64_t)(((unsigned __int128)u * (unsigned __int128)n) >> 53);
-}
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
@@ -265,85 +251,11 @@ cavi_status finish_init(Handle *h)
     return CAVI_OK;
 }
 
-// k-means++ seeds of dataset 0 driven from the host (many workgroups per pass)
-cavi_status init_single(Handle *h, uint64_t seed)
+// standard initialisation of every dataset: k-means++ seeds on the device (dataset b uses the
+// SplitMix64 state seed + b), hard nearest-seed statistics, one update
+cavi_status init_all(Handle *h, uint64_t seed)
 {
-    const Shape &s = h->s;
-    const Bufs &B = h->b;
-    hipStream_t st = h->stream;
-    const int64_t N = h->ds[0].N;
-    const int nblk = (int)((N + kBlock - 1) / kBlock);
-    uint64_t rng = seed;
-    int clog2n = 0;
-    while (((int64_t)1 << clog2n) < N) ++clog2n;
-    std::vector<double> bmax(nblk), blockd(kBlock);
-    std::vector<unsigned long long> bsum(nblk);
-    auto put_seed = [&](int j, int64_t row) -> cavi_status {
-        HIPCHK(hipMemcpyAsync(B.seeds + (size_t)j * s.G, B.x + (size_t)row * s.G, sizeof(float) * s.G,
-                              hipMemcpyDeviceToDevice, st));
-        return CAVI_OK;
-    };
-    int64_t row = (int64_t)scaled_draw(rng, (uint64_t)N);
-    cavi_status rs = put_seed(0, row);
-    if (rs != CAVI_OK) return rs;
-    HIPCHK(launch_d2(s, B, 0, 0, 1, st));
-    for (int j = 1; j < h->ds[0].K; ++j) {
-        HIPCHK(hipMemcpyAsync(bmax.data(), B.blockmax, sizeof(double) * nblk, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        double mx = 0.0;
-        for (int i = 0; i < nblk; ++i) mx = std::max(mx, bmax[i]);
-        if (mx == 0.0) {
-            row = (int64_t)scaled_draw(rng, (uint64_t)N);
-        } else {
-            int E;
-            frexp(mx, &E);
-            const int e = 62 - E - clog2n;
-            HIPCHK(launch_wsum(s, B, 0, e, st));
-            HIPCHK(hipMemcpyAsync(bsum.data(), B.blocksum, sizeof(unsigned long long) * nblk, hipMemcpyDeviceToHost,
-                                  st));
-            HIPCHK(hipStreamSynchronize(st));
-            unsigned long long W = 0;
-            for (int i = 0; i < nblk; ++i) W += bsum[i];
-            const uint64_t t = scaled_draw(rng, W);
-            unsigned long long cum = 0;
-            int blk = nblk - 1;
-            for (int i = 0; i < nblk; ++i) {
-                if (cum + bsum[i] > t) {
-                    blk = i;
-                    break;
-                }
-                cum += bsum[i];
-            }
-            const int64_t base = (int64_t)blk * kBlock;
-            const int cnt = (int)std::min<int64_t>(kBlock, N - base);
-            HIPCHK(hipMemcpyAsync(blockd.data(), B.mind2 + base, sizeof(double) * cnt, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            row = base + cnt - 1;
-            for (int i = 0; i < cnt; ++i) {
-                cum += (unsigned long long)floor(ldexp(blockd[i], e));
-                if (cum > t) {
-                    row = base + i;
-                    break;
-                }
-            }
-        }
-        rs = put_seed(j, row);
-        if (rs != CAVI_OK) return rs;
-        HIPCHK(launch_d2(s, B, 0, j, 0, st));
-    }
-    return finish_init(h);
-}
-
-// k-means++ of every dataset on the device; dataset b uses SplitMix64 state seed + b
-cavi_status init_batch(Handle *h, uint64_t seed)
-{
-    std::vector<unsigned long long> seeds(h->s.B);
-    for (int i = 0; i < h->s.B; ++i) seeds[i] = seed + (uint64_t)i;
-    // the totals array is free during initialisation: stage the seeds there
-    unsigned long long *dseeds = (unsigned long long *)h->b.totals;
-    HIPCHK(hipMemcpyAsync(dseeds, seeds.data(), sizeof(unsigned long long) * h->s.B, hipMemcpyHostToDevice,
-                          h->stream));
-    HIPCHK(launch_kmeanspp_batch(h->s, h->b, dseeds, h->stream));
+    HIPCHK(launch_kmeanspp(h->s, h->b, (unsigned long long)seed, h->stream));
     return finish_init(h);
 }
 
@@ -537,7 +449,7 @@ cavi_status cavi_get_prior_mean(cavi_ctx *ctx, double *m0_host)
 cavi_status cavi_init_standard(cavi_ctx *ctx, uint64_t seed)
 {
     if (!ctx) return fail(CAVI_E_INVAL, "ctx is NULL");
-    return init_single(&ctx->h, seed);
+    return init_all(&ctx->h, seed);
 }
 
 cavi_status cavi_set_state(cavi_ctx *ctx, const double *alpha, const double *m, const double *beta,
@@ -654,7 +566,7 @@ cavi_status cavi_batch_destroy(cavi_batch *bt)
 cavi_status cavi_batch_init_standard(cavi_batch *bt, uint64_t seed)
 {
     if (!bt) return fail(CAVI_E_INVAL, "batch is NULL");
-    return init_batch(&bt->h, seed);
+    return init_all(&bt->h, seed);
 }
 
 cavi_status cavi_batch_set_state(cavi_batch *bt, int32_t b, const double *alpha, const double *m,

@@ -81,8 +81,8 @@ struct Bufs {
     Ctl *ctl;             // B
     int32_t *count;       // 1: datasets still sweeping
     double *mind2;        // Ntot             (initialisation)
-    double *blockmax;     // ceil(Nmax / 256)
-    unsigned long long *blocksum;  // ceil(Nmax / 256)
+    double *blockmax;     // nchunk           (initialisation)
+    unsigned long long *blocksum;  // nchunk  (initialisation)
     double *colpart;      // nchunk x G      (prior centre)
 };
 
@@ -110,7 +110,7 @@ hipError_t prepare_kernels();
 hipError_t launch_estep_stats(const Shape &s, const Bufs &b, int init_mode, hipStream_t st);
 // Tiled E-step kernel (estep_tiled.hip) for G in {16,32,48,64,96,128} and small K.
 bool tiled_supported(int K, int G);
-hipError_t launch_estep_tiled(const Shape &s, const Bufs &b, hipStream_t st);
+hipError_t launch_estep_tiled(const Shape &s, const Bufs &b, int init_mode, hipStream_t st);
 hipError_t launch_reduce(const Shape &s, const Bufs &b, int init_mode, hipStream_t st);
 hipError_t launch_mstep(const Shape &s, const Bufs &b, const Prior &p, int init_mode, hipStream_t st);
 hipError_t launch_coef(const Shape &s, const Bufs &b, hipStream_t st);
@@ -119,13 +119,9 @@ hipError_t launch_resp(const Shape &s, const Bufs &b, float *r, hipStream_t st);
 hipError_t launch_ctl_begin(const Shape &s, const Bufs &b, int max_call, int stop_on_conv, double tol, int reset,
                             hipStream_t st);
 hipError_t launch_count_active(const Shape &s, const Bufs &b, hipStream_t st);
-// k-means++ of one dataset driven from the host (large N): running minimum
-// of the squared distances to the seeds and per-block sums of the weights.
-hipError_t launch_d2(const Shape &s, const Bufs &b, int dataset, int seed_index, int first, hipStream_t st);
-hipError_t launch_wsum(const Shape &s, const Bufs &b, int dataset, int e, hipStream_t st);
-// k-means++ of every dataset on the device, one workgroup per dataset.
-hipError_t launch_kmeanspp_batch(const Shape &s, const Bufs &b, const unsigned long long *seeds_dev,
-                                 hipStream_t st);
+// k-means++ seeds of every dataset (dataset b: SplitMix64 state seed + b), a few launches
+// per seed and no host synchronisation; leaves the seeds in b.seeds.
+hipError_t launch_kmeanspp(const Shape &s, const Bufs &b, unsigned long long seed, hipStream_t st);
 
 // Learned warm start (warmstart.hip).
 hipError_t launch_features(const float *x, const int64_t *row_off, int B, int G, float *feat, hipStream_t st);

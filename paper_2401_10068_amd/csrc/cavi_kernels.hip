@@ -295,160 +295,213 @@ __global__ __launch_bounds__(kBlock) void k_colmean(Shape s, Bufs bf)
 }
 
 // ---------------------------------------------------------------------------------------------
-// k-means++ helpers for one dataset, driven from the host: running minimum of
-// the squared distance to the seeds chosen so far (mind2, indexed by the
-// dataset's row), its per-block maximum, and per-block sums of the integer
-// weights floor(minD2 * 2^e).
-__global__ __launch_bounds__(kBlock) void k_d2(Shape s, Bufs bf, int bi, int seed_index, int first)
+// k-means++ seeds (D^2 sampling) of every dataset of a batch, on the device, with many
+// workgroups per dataset: one pass over all rows per seed.  Definition (shared with the
+// oracle): the SplitMix64 state of dataset b draws the first seed row floor(u N); each later
+// seed is the smallest row whose cumulative integer weight floor(minD2 2^e) exceeds
+// floor(u W), W the sum of the weights and e = 62 - E - ceil(log2 N) for the largest minD2 =
+// f 2^E (f in [1/2, 1)); if every minD2 is 0 the row is floor(u N) again.  minD2 is the FP64
+// squared distance to the nearest seed so far, genes added in order.
+//
+// Per-dataset state, in the totals array (free during initialisation):
+//   [0] SplitMix64 state, [1] chosen row, [2] e (or kNoWeights when every minD2 is 0).
+// Per-chunk maxima and weight sums: blockmax / blocksum, indexed by the global chunk.
+namespace {
+constexpr long long kNoWeights = -1000000;
+
+__device__ __forceinline__ unsigned long long *pp_state(const Shape &s, const Bufs &bf, int bi)
 {
-    // thread t owns row blockIdx.x * 256 + t; the rows are staged through LDS 32 genes at a
-    // time (coalesced loads), and each thread adds its row's squared differences in gene
-    // order, exactly as sqdist64 does
+    return (unsigned long long *)(bf.totals + (size_t)bi * s.Smax);
+}
+
+__device__ __forceinline__ int ceil_log2(int64_t n)
+{
+    int c = 0;
+    while (((int64_t)1 << c) < n) ++c;
+    return c;
+}
+
+// inclusive prefix sum over the 64 lanes of a wave (exact: integers)
+__device__ __forceinline__ unsigned long long wave_scan(unsigned long long v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned long long o = __shfl_up(v, off, 64);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+}  // namespace
+
+__global__ void k_pp_begin(Shape s, Bufs bf, unsigned long long seed)
+{
+    const int bi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bi >= s.B) return;
+    unsigned long long *st = pp_state(s, bf, bi);
+    unsigned long long rng = seed + (unsigned long long)bi;
+    st[1] = scaled_draw(rng, (unsigned long long)bf.ds[bi].N);
+    st[0] = rng;
+}
+
+// one workgroup per chunk: minD2 against seed j (rows staged through LDS 32 genes at a time),
+// the chunk maximum, and the copy of the seed row into the seed table
+__global__ __launch_bounds__(kBlock) void k_pp_d2(Shape s, Bufs bf, int j)
+{
     constexpr int kSlab = 32;
     __shared__ float xs[kBlock][kSlab + 1];
     __shared__ float sd[kSlab];
     __shared__ double red[kBlock];
+    const int chunk = blockIdx.x, tid = threadIdx.x, G = s.G;
+    const int bi = bf.chunk_ds[chunk];
     const Ds d = bf.ds[bi];
-    const int G = s.G, tid = threadIdx.x;
-    const int64_t n0 = (int64_t)blockIdx.x * kBlock;
-    const int nr = (int)max((int64_t)0, min((int64_t)kBlock, (int64_t)d.N - n0));
-    const float *seed = bf.seeds + ((size_t)bi * s.Kmax + seed_index) * G;
-    const float *xb = bf.x + (d.row0 + n0) * G;
-    double acc = 0.0;
-    for (int g0 = 0; g0 < G; g0 += kSlab) {
-        const int w = min(kSlab, G - g0);
-        for (int e = tid; e < kBlock * kSlab; e += kBlock) {
-            const int r = e / kSlab, c = e - r * kSlab;
-            if (r < nr && c < w) xs[r][c] = xb[(int64_t)r * G + g0 + c];
-        }
-        if (tid < w) sd[tid] = seed[g0 + tid];
-        __syncthreads();
-        if (tid < nr) {
-#pragma clang fp contract(off)
-            for (int c = 0; c < w; ++c) {
-                const double dd = (double)xs[tid][c] - (double)sd[c];
-                acc = acc + dd * dd;
+    if (j >= d.K) return;
+    const int64_t row = (int64_t)pp_state(s, bf, bi)[1];
+    const float *seed = bf.x + (d.row0 + row) * G;
+    if (chunk == d.chunk0)
+        for (int g = tid; g < G; g += kBlock) bf.seeds[((size_t)bi * s.Kmax + j) * G + g] = seed[g];
+    const int64_t c0 = (int64_t)(chunk - d.chunk0) * kChunkRows;
+    const int nrc = (int)min((int64_t)kChunkRows, (int64_t)d.N - c0);
+    double mx = 0.0;
+    for (int r0 = 0; r0 < nrc; r0 += kBlock) {
+        const int nr = min(kBlock, nrc - r0);
+        const float *xb = bf.x + (d.row0 + c0 + r0) * G;
+        double acc = 0.0;
+        for (int g0 = 0; g0 < G; g0 += kSlab) {
+            const int w = min(kSlab, G - g0);
+            for (int e = tid; e < kBlock * kSlab; e += kBlock) {
+                const int r = e / kSlab, c = e - r * kSlab;
+                if (r < nr && c < w) xs[r][c] = xb[(int64_t)r * G + g0 + c];
             }
+            if (tid < w) sd[tid] = seed[g0 + tid];
+            __syncthreads();
+            if (tid < nr) {
+#pragma clang fp contract(off)
+                for (int c = 0; c < w; ++c) {
+                    const double dd = (double)xs[tid][c] - (double)sd[c];
+                    acc = acc + dd * dd;
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
+        if (tid < nr) {
+            double *m = bf.mind2 + d.row0 + c0 + r0 + tid;
+            const double v = j == 0 ? acc : fmin(*m, acc);
+            *m = v;
+            mx = fmax(mx, v);
+        }
     }
-    double v = 0.0;
-    if (tid < nr) {
-        const int64_t n = n0 + tid;
-        v = first ? acc : fmin(bf.mind2[n], acc);
-        bf.mind2[n] = v;
-    }
-    red[tid] = v;
+    red[tid] = mx;
     __syncthreads();
     for (int off = kBlock / 2; off > 0; off >>= 1) {
         if (tid < off) red[tid] = fmax(red[tid], red[tid + off]);
         __syncthreads();
     }
-    if (tid == 0) bf.blockmax[blockIdx.x] = red[0];
+    if (tid == 0) bf.blockmax[chunk] = red[0];
 }
 
-__global__ __launch_bounds__(kBlock) void k_wsum(Shape s, Bufs bf, int bi, int e)
+// one wave per dataset: e from the largest minD2 of its chunks
+__global__ __launch_bounds__(64) void k_pp_exp(Shape s, Bufs bf, int j)
+{
+    const int bi = blockIdx.x, lane = threadIdx.x;
+    const Ds d = bf.ds[bi];
+    if (j >= d.K) return;
+    double mx = 0.0;
+    for (int c = lane; c < d.nchunk; c += 64) mx = fmax(mx, bf.blockmax[d.chunk0 + c]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if (lane == 0) {
+        long long e = kNoWeights;
+        if (mx > 0.0) {
+            int E;
+            frexp(mx, &E);
+            e = 62 - E - ceil_log2(d.N);
+        }
+        pp_state(s, bf, bi)[2] = (unsigned long long)e;
+    }
+}
+
+// one workgroup per chunk: sum of the integer weights floor(minD2 2^e)
+__global__ __launch_bounds__(kBlock) void k_pp_wsum(Shape s, Bufs bf, int j)
 {
     __shared__ unsigned long long red[kBlock];
+    const int chunk = blockIdx.x, tid = threadIdx.x;
+    const int bi = bf.chunk_ds[chunk];
     const Ds d = bf.ds[bi];
-    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= d.K) return;
+    const long long e = (long long)pp_state(s, bf, bi)[2];
+    if (e == kNoWeights) return;
+    const int64_t c0 = (int64_t)(chunk - d.chunk0) * kChunkRows;
+    const int nrc = (int)min((int64_t)kChunkRows, (int64_t)d.N - c0);
+    const double *m = bf.mind2 + d.row0 + c0;
     unsigned long long w = 0;
-    if (n < d.N) w = (unsigned long long)floor(ldexp(bf.mind2[n], e));
-    red[threadIdx.x] = w;
+    for (int r = tid; r < nrc; r += kBlock) w += (unsigned long long)floor(ldexp(m[r], (int)e));
+    red[tid] = w;
     __syncthreads();
     for (int off = kBlock / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        if (tid < off) red[tid] += red[tid + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) bf.blocksum[blockIdx.x] = red[0];
+    if (tid == 0) bf.blocksum[chunk] = red[0];
 }
 
-// ---------------------------------------------------------------------------------------------
-// k-means++ seeds of every dataset, one workgroup per dataset, with the same
-// definition as the host-driven path: first seed row floor(u N), then the
-// smallest row whose cumulative integer weight floor(minD2 2^e) exceeds
-// floor(u W), with e the largest exponent keeping W below 2^62.  Thread t
-// owns a contiguous segment of rows so the cumulative sum follows row order.
-__global__ __launch_bounds__(kBlock) void k_kmeanspp_batch(Shape s, Bufs bf, const unsigned long long *rng_seeds)
+// one wave per dataset: the draw for seed j; the chunk holding it, then the row
+__global__ __launch_bounds__(64) void k_pp_draw(Shape s, Bufs bf, int j)
 {
-    __shared__ double dred[kBlock];
-    __shared__ unsigned long long ured[kBlock];
-    __shared__ int64_t pick;
-    const int bi = blockIdx.x, tid = threadIdx.x, G = s.G;
+    const int bi = blockIdx.x, lane = threadIdx.x;
     const Ds d = bf.ds[bi];
-    const int64_t N = d.N;
-    const float *xb = bf.x + d.row0 * G;
-    double *mind = bf.mind2 + d.row0;
-    float *seeds = bf.seeds + (size_t)bi * s.Kmax * G;
-    unsigned long long rng = rng_seeds[bi];
-    int clog2n = 0;
-    while (((int64_t)1 << clog2n) < N) ++clog2n;
-    const int64_t seg = (N + kBlock - 1) / kBlock;
-    const int64_t n0 = min(N, seg * tid), n1 = min(N, seg * (tid + 1));
-
-    int64_t row = (int64_t)scaled_draw(rng, (unsigned long long)N);
-    for (int j = 0; j < d.K; ++j) {
-        if (j > 0) {
-            // maximum of the running minimum
-            double mx = 0.0;
-            for (int64_t n = n0; n < n1; ++n) mx = fmax(mx, mind[n]);
-            dred[tid] = mx;
-            __syncthreads();
-            for (int off = kBlock / 2; off > 0; off >>= 1) {
-                if (tid < off) dred[tid] = fmax(dred[tid], dred[tid + off]);
-                __syncthreads();
-            }
-            mx = dred[0];
-            __syncthreads();
-            if (mx == 0.0) {
-                row = (int64_t)scaled_draw(rng, (unsigned long long)N);
-            } else {
-                int E;
-                frexp(mx, &E);
-                const int e = 62 - E - clog2n;
-                unsigned long long ws = 0;
-                for (int64_t n = n0; n < n1; ++n) ws += (unsigned long long)floor(ldexp(mind[n], e));
-                ured[tid] = ws;
-                __syncthreads();
-                if (tid == 0) {
-                    unsigned long long W = 0;
-                    for (int i = 0; i < kBlock; ++i) W += ured[i];
-                    const unsigned long long t = scaled_draw(rng, W);
-                    // segment holding the draw, then the row within it
-                    unsigned long long cum = 0;
-                    int seg_i = kBlock - 1;
-                    for (int i = 0; i < kBlock; ++i) {
-                        if (cum + ured[i] > t) {
-                            seg_i = i;
-                            break;
-                        }
-                        cum += ured[i];
-                    }
-                    int64_t r = min(N, seg * (seg_i + 1)) - 1;
-                    for (int64_t n = min(N, seg * seg_i); n < min(N, seg * (seg_i + 1)); ++n) {
-                        cum += (unsigned long long)floor(ldexp(mind[n], e));
-                        if (cum > t) {
-                            r = n;
-                            break;
-                        }
-                    }
-                    pick = r;
-                } else {
-                    // keep the generator state in step on every thread
-                    (void)scaled_draw(rng, 1);
-                }
-                __syncthreads();
-                row = pick;
-                __syncthreads();
-            }
+    if (j >= d.K) return;
+    unsigned long long *st = pp_state(s, bf, bi);
+    unsigned long long rng = st[0];
+    const long long e = (long long)st[2];
+    if (e == kNoWeights) {
+        const unsigned long long r = scaled_draw(rng, (unsigned long long)d.N);
+        if (lane == 0) {
+            st[1] = r;
+            st[0] = rng;
         }
-        for (int g = tid; g < G; g += kBlock) seeds[(size_t)j * G + g] = xb[row * G + g];
-        __syncthreads();
-        for (int64_t n = n0; n < n1; ++n) {
-            const double d2 = sqdist64(xb + n * G, seeds + (size_t)j * G, G);
-            mind[n] = (j == 0) ? d2 : fmin(mind[n], d2);
+        return;
+    }
+    unsigned long long W = 0;
+    for (int c = lane; c < d.nchunk; c += 64) W += bf.blocksum[d.chunk0 + c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) W += __shfl_xor(W, off, 64);
+    const unsigned long long t = scaled_draw(rng, W);  // every lane: same state, same draw
+    // chunk: the first whose cumulative sum exceeds t
+    unsigned long long base = 0;
+    int ch = d.nchunk - 1;
+    for (int c0 = 0; c0 < d.nchunk; c0 += 64) {
+        const int c = c0 + lane;
+        const unsigned long long v = c < d.nchunk ? bf.blocksum[d.chunk0 + c] : 0ull;
+        const unsigned long long cum = base + wave_scan(v);
+        const unsigned long long hit = __ballot(c < d.nchunk && cum > t);
+        if (hit) {
+            const int l = __builtin_ctzll(hit);
+            ch = c0 + l;
+            base = __shfl(cum, l, 64) - __shfl(v, l, 64);
+            break;
         }
-        __syncthreads();
+        base = __shfl(cum, 63, 64);
+    }
+    // row within the chunk
+    const int64_t r0 = (int64_t)ch * kChunkRows;
+    const int nrc = (int)min((int64_t)kChunkRows, (int64_t)d.N - r0);
+    const double *m = bf.mind2 + d.row0 + r0;
+    int64_t row = r0 + nrc - 1;
+    for (int q0 = 0; q0 < nrc; q0 += 64) {
+        const int q = q0 + lane;
+        const unsigned long long v = q < nrc ? (unsigned long long)floor(ldexp(m[q], (int)e)) : 0ull;
+        const unsigned long long cum = base + wave_scan(v);
+        const unsigned long long hit = __ballot(q < nrc && cum > t);
+        if (hit) {
+            row = r0 + q0 + __builtin_ctzll(hit);
+            break;
+        }
+        base = __shfl(cum, 63, 64);
+    }
+    if (lane == 0) {
+        st[1] = (unsigned long long)row;
+        st[0] = rng;
     }
 }
 
@@ -506,7 +559,7 @@ static size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
 size_t workspace_bytes(const Shape &s)
 {
     const size_t B = s.B, K = (size_t)s.B * s.Kmax, KG = K * s.G, G = s.G;
-    const size_t nblk = (s.Nmax + kBlock - 1) / kBlock;
+    const size_t nblk = s.nchunk;  // per-chunk maxima and weight sums (initialisation)
     size_t n = 0;
     n += al(B * sizeof(Ds)) + al((size_t)s.nchunk * 4);
     n += 2 * al(K * 8);                // alpha, nalpha
@@ -526,7 +579,7 @@ size_t workspace_bytes(const Shape &s)
 void carve(const Shape &s, void *ws, Bufs &b)
 {
     const size_t B = s.B, K = (size_t)s.B * s.Kmax, KG = K * s.G, G = s.G;
-    const size_t nblk = (s.Nmax + kBlock - 1) / kBlock;
+    const size_t nblk = s.nchunk;  // per-chunk maxima and weight sums (initialisation)
     char *p = (char *)ws;
     auto take = [&](size_t bytes) {
         void *r = p;
@@ -600,7 +653,7 @@ static hipError_t launch_estep_t(const Shape &s, const Bufs &b, int init_mode, h
 
 hipError_t launch_estep_stats(const Shape &s, const Bufs &b, int init_mode, hipStream_t st)
 {
-    if (!init_mode && tiled_supported(s.Kmax, s.G)) return launch_estep_tiled(s, b, st);
+    if (tiled_supported(s.Kmax, s.G)) return launch_estep_tiled(s, b, init_mode, st);
     switch (s.kt) {
     case 4: return launch_estep_t<4>(s, b, init_mode, st);
     case 8: return launch_estep_t<8>(s, b, init_mode, st);
@@ -619,23 +672,17 @@ hipError_t launch_prior_mean(const Shape &s, const Bufs &b, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_d2(const Shape &s, const Bufs &b, int dataset, int seed_index, int first, hipStream_t st)
+hipError_t launch_kmeanspp(const Shape &s, const Bufs &b, unsigned long long seed, hipStream_t st)
 {
-    const int nblk = (int)((s.Nmax + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_d2, dim3(nblk), dim3(kBlock), 0, st, s, b, dataset, seed_index, first);
-    return hipGetLastError();
-}
-
-hipError_t launch_wsum(const Shape &s, const Bufs &b, int dataset, int e, hipStream_t st)
-{
-    const int nblk = (int)((s.Nmax + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_wsum, dim3(nblk), dim3(kBlock), 0, st, s, b, dataset, e);
-    return hipGetLastError();
-}
-
-hipError_t launch_kmeanspp_batch(const Shape &s, const Bufs &b, const unsigned long long *seeds_dev, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_kmeanspp_batch, dim3(s.B), dim3(kBlock), 0, st, s, b, seeds_dev);
+    hipLaunchKernelGGL(k_pp_begin, dim3((s.B + 255) / 256), dim3(256), 0, st, s, b, seed);
+    for (int j = 0; j < s.Kmax; ++j) {
+        if (j > 0) {
+            hipLaunchKernelGGL(k_pp_exp, dim3(s.B), dim3(64), 0, st, s, b, j);
+            hipLaunchKernelGGL(k_pp_wsum, dim3(s.nchunk), dim3(kBlock), 0, st, s, b, j);
+            hipLaunchKernelGGL(k_pp_draw, dim3(s.B), dim3(64), 0, st, s, b, j);
+        }
+        hipLaunchKernelGGL(k_pp_d2, dim3(s.nchunk), dim3(kBlock), 0, st, s, b, j);
+    }
     return hipGetLastError();
 }
 

@@ -112,6 +112,19 @@ __device__ __forceinline__ float tail_sum(const float *xr, const float *pr, int 
     return s;
 }
 
+// FP64 squared distance of an LDS row to a seed stored at the even entries of a table row,
+// genes added in order (the definition of the initialisation's nearest seed)
+__device__ __forceinline__ double sqdist_lds(const float *x, const float *t, int G)
+{
+#pragma clang fp contract(off)
+    double s = 0.0;
+    for (int g = 0; g < G; ++g) {
+        const double d = (double)x[g] - (double)t[2 * g];
+        s = s + d * d;
+    }
+    return s;
+}
+
 // Workgroup barrier that waits only for this wave's LDS operations: the
 // prefetch of the next tile (global loads) stays in flight across it.
 __device__ __forceinline__ void lds_barrier()
@@ -135,7 +148,7 @@ __device__ __forceinline__ double wave_sum(double v)
 
 }  // namespace
 
-template <int KT, int G>
+template <int KT, int G, bool INIT>
 __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
 {
     using C = Cfg<KT, G>;
@@ -154,7 +167,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
     for (int chunk = blockIdx.x; chunk < s.nchunk; chunk += gridDim.x) {
         const int bi = bf.chunk_ds[chunk];
         const Ds d = bf.ds[bi];
-        if (sweep_skipped(bf.ctl + bi)) continue;
+        if (!INIT && sweep_skipped(bf.ctl + bi)) continue;
         const int K = d.K, KG = K * G;
         // the chunk's first tile is requested before anything else is read
         const int64_t r0 = d.row0 + (int64_t)(chunk - d.chunk0) * kChunkRows;
@@ -170,6 +183,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
         const float *__restrict__ cc = bf.cc + kb;
         const float *__restrict__ hq = bf.hq + 2 * kb * G;
         const float *__restrict__ mf = bf.mf + kb * G;
+        const float *__restrict__ seedp = bf.seeds + kb * G;
         double *__restrict__ partials = bf.partials;
 
         // coefficients: every load unconditional (indexes clamped into the dataset's arrays),
@@ -179,8 +193,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
 #pragma unroll
         for (int u = 0; u < NPT; ++u) {
             const int ic = min(tid + u * kBlock, KG - 1);
-            hv[u] = hq[2 * ic];
-            qv[u] = hq[2 * ic + 1];
+            // initialisation: the table holds the seed rows instead of (h, q)
+            hv[u] = INIT ? seedp[ic] : hq[2 * ic];
+            qv[u] = INIT ? 0.f : hq[2 * ic + 1];
         }
         const float ccv = cc[min(tid, K - 1)];
         float mfv[KT][GS];
@@ -230,6 +245,30 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
             const int j = jbase + jl;
             const bool act = jl < nj;
 
+            float rv[KT];
+            uint32_t mk = 0;
+#pragma unroll
+            for (int k = 0; k < KT; ++k) rv[k] = 0.f;
+            if (INIT) {
+                // hard nearest seed by the FP64 squared distance, genes added in order, ties to
+                // the lowest seed (one lane per row)
+                if (act && half == 0) {
+                    const float *xr0 = xs + j * XS;
+                    int best = 0;
+                    double bd = 0.0;
+                    for (int q = 0; q < K; ++q) {
+                        const double d2 = sqdist_lds(xr0, pt + q * PS, G);
+                        if (q == 0 || d2 < bd) {
+                            bd = d2;
+                            best = q;
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < KT; ++k)
+                        if (k == best) t0[k] += 1.f;
+                    mk = (1u << best) | kOneHot;
+                }
+            } else {
             // A. screen: partial sums over the first GB genes; lane (row j, half) takes
             //    subpopulations half, half + 2, ...
             {
@@ -320,10 +359,6 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
             __builtin_amdgcn_wave_barrier();
 
             // log-sum-exp over the computed set (lanes jl < 32 own the rows)
-            float rv[KT];
-            uint32_t mk = 0;
-#pragma unroll
-            for (int k = 0; k < KT; ++k) rv[k] = 0.f;
             if (act && half == 0) {
                 float l[KT];
 #pragma unroll
@@ -361,6 +396,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
                 }
                 hacc += (double)h;
             }
+
+            }  // phases A, B and log-sum-exp
 
             // C. statistics over the same rows, lanes over genes.  For each subpopulation
             //    (a static loop, so the sums stay in registers) walk the rows whose
@@ -448,23 +485,26 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
 namespace {
 
 template <int KT, int G>
-hipError_t launch_t(const Shape &s, const Bufs &b, hipStream_t st)
+hipError_t launch_t(const Shape &s, const Bufs &b, int init_mode, hipStream_t st)
 {
     constexpr int lds = Cfg<KT, G>::LDS_BYTES;
-    hipLaunchKernelGGL((k_estep_tiled<KT, G>), dim3(s.nchunk), dim3(kBlock), lds, st, s, b);
+    if (init_mode)
+        hipLaunchKernelGGL((k_estep_tiled<KT, G, true>), dim3(s.nchunk), dim3(kBlock), lds, st, s, b);
+    else
+        hipLaunchKernelGGL((k_estep_tiled<KT, G, false>), dim3(s.nchunk), dim3(kBlock), lds, st, s, b);
     return hipGetLastError();
 }
 
 template <int KT>
-hipError_t launch_g(const Shape &s, const Bufs &b, hipStream_t st)
+hipError_t launch_g(const Shape &s, const Bufs &b, int init_mode, hipStream_t st)
 {
     switch (s.G) {
-    case 16: return launch_t<KT, 16>(s, b, st);
-    case 32: return launch_t<KT, 32>(s, b, st);
-    case 48: return launch_t<KT, 48>(s, b, st);
-    case 64: return launch_t<KT, 64>(s, b, st);
-    case 96: return launch_t<KT, 96>(s, b, st);
-    case 128: return launch_t<KT, 128>(s, b, st);
+    case 16: return launch_t<KT, 16>(s, b, init_mode, st);
+    case 32: return launch_t<KT, 32>(s, b, init_mode, st);
+    case 48: return launch_t<KT, 48>(s, b, init_mode, st);
+    case 64: return launch_t<KT, 64>(s, b, init_mode, st);
+    case 96: return launch_t<KT, 96>(s, b, init_mode, st);
+    case 128: return launch_t<KT, 128>(s, b, init_mode, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -487,17 +527,17 @@ bool tiled_supported(int K, int G)
     return lds_bytes(kt, G) <= (g_lds_limit > 0 ? g_lds_limit : 65536);
 }
 
-hipError_t launch_estep_tiled(const Shape &s, const Bufs &b, hipStream_t st)
+hipError_t launch_estep_tiled(const Shape &s, const Bufs &b, int init_mode, hipStream_t st)
 {
     switch (s.kt) {
-    case 4: return launch_g<4>(s, b, st);
-    case 8: return launch_g<8>(s, b, st);
+    case 4: return launch_g<4>(s, b, init_mode, st);
+    case 8: return launch_g<8>(s, b, init_mode, st);
     case 16:
         switch (s.G) {
-        case 16: return launch_t<16, 16>(s, b, st);
-        case 32: return launch_t<16, 32>(s, b, st);
-        case 48: return launch_t<16, 48>(s, b, st);
-        case 64: return launch_t<16, 64>(s, b, st);
+        case 16: return launch_t<16, 16>(s, b, init_mode, st);
+        case 32: return launch_t<16, 32>(s, b, init_mode, st);
+        case 48: return launch_t<16, 48>(s, b, init_mode, st);
+        case 64: return launch_t<16, 64>(s, b, init_mode, st);
         default: return hipErrorInvalidValue;
         }
     default: return hipErrorInvalidValue;
