@@ -92,6 +92,7 @@ def batch_bench(args) -> int:
     sw, el, nconv = bt.run(args.max_sweeps, 1e-6)
     torch.cuda.synchronize()
     t_run = time.perf_counter() - t0
+    sched = bt.schedule()
     bt.close()
     nkg = float((sw.astype(np.float64) * Ns * Ks * G).sum())
     bytes_read = float((sw.astype(np.float64) * Ns * 4 * G).sum())
@@ -125,7 +126,7 @@ def batch_bench(args) -> int:
                                f"K in {{{Ks.min()}..{Ks.max()}}}, G={G}, seed {seed}, run to 1e-6"},
         "batched": {"init_s": t_init, "run_s": t_run, "converged": nconv, "datasets": int(Ns.size),
                     "sweeps_total": int(sw.sum()), "sweeps_median": float(np.median(sw)), "sweeps_max": int(sw.max()),
-                    "effective_GBps": bytes_read / t_run / 1e9},
+                    "effective_GBps": bytes_read / t_run / 1e9, "estep_schedule": sched},
         "plain_one_at_a_time": {"sample": int(idx.size), "sample_s": t_plain,
                                 "extrapolated_s": t_plain / frac, "sweeps_median": float(np.median(plain_sw)),
                                 "max_rel_elbo_diff_vs_batched": max_rel},
@@ -279,6 +280,7 @@ def main() -> int:
     sec = time.perf_counter() - t0
 
     est_ms = cx.profile_estep(20)
+    sched, sched_ms = cx.schedule()
     bytes_per_sweep = 4.0 * N * G  # X read once per sweep, FP32
     achieved = bytes_per_sweep / (est_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload)
@@ -312,6 +314,8 @@ def main() -> int:
             "traffic": traffic,
             "avg_ms": est_ms,
             "bytes_per_launch": bytes_per_sweep,
+            "schedule": sched,
+            "schedule_ms": sched_ms,
         },
     }
     cx.close()

@@ -247,6 +247,21 @@ cavi_status cavi_mlp_adamw(cavi_mlp *net, float lr, float beta1, float beta2, fl
                            float weight_decay);
 cavi_status cavi_mlp_destroy(cavi_mlp *net);
 
+/* ------------------------------------------------------------------------
+ * E-step schedule (autotuner).  For the shapes of the tiled E-step (G in
+ * {16, 32, 48, 64, 96, 128}, K <= 16) two schedules give bitwise the same
+ * results: 0 keeps the exact-term loads, centres and responsibilities in
+ * registers; 1 keeps them in LDS and needs fewer registers (more waves per
+ * SIMD).  At the first sweep, run or profile call the library times both on
+ * the handle's data and keeps the faster one; cavi_*set_schedule forces one
+ * (-1: tune again at the next call).  ms (NULL or 2 entries) receives the
+ * measured average E-step times of schedules 0 and 1 (0 if not measured).
+ * ------------------------------------------------------------------------ */
+cavi_status cavi_get_schedule(cavi_ctx *ctx, int32_t *schedule, float *ms);
+cavi_status cavi_set_schedule(cavi_ctx *ctx, int32_t schedule);
+cavi_status cavi_batch_get_schedule(cavi_batch *bt, int32_t *schedule, float *ms);
+cavi_status cavi_batch_set_schedule(cavi_batch *bt, int32_t schedule);
+
 /* Thread-local text of the last error ("" if none). */
 const char *cavi_last_error(void);
 

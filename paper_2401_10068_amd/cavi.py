@@ -66,6 +66,10 @@ def lib():
             "cavi_batch_run": (st, [vp, C.c_int32, C.c_double, vp, vp, C.POINTER(C.c_int32)]),
             "cavi_batch_destroy": (st, [vp]),
             "cavi_batch_set_state_warm": (st, [vp, vp, C.c_int32]),
+            "cavi_get_schedule": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
+            "cavi_set_schedule": (st, [vp, C.c_int32]),
+            "cavi_batch_get_schedule": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
+            "cavi_batch_set_schedule": (st, [vp, C.c_int32]),
             "cavi_features": (st, [vp, vp, C.c_int32, C.c_int32, vp, vp]),
             "cavi_warm_targets": (st, [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp]),
             "cavi_mlp_create": (st, [C.POINTER(vp), C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
@@ -198,6 +202,13 @@ def cavi_destroy(h):
         _check(lib().cavi_destroy(h))
 
 
+def _get_schedule(fn, h):
+    sc = C.c_int32(0)
+    ms = (C.c_float * 2)()
+    _check(fn(h, C.byref(sc), ms))
+    return int(sc.value), [float(ms[0]), float(ms[1])]
+
+
 # ----------------------------------------------------------------------------- convenience
 class Cavi:
     """Owning wrapper: keeps the data tensor and the workspace alive."""
@@ -245,6 +256,13 @@ class Cavi:
 
     def prior_mean(self):
         return cavi_get_prior_mean(self.h, self.G)
+
+    def schedule(self):
+        """``(schedule, [ms of schedule 0, ms of schedule 1])`` of the E-step autotuner."""
+        return _get_schedule(lib().cavi_get_schedule, self.h)
+
+    def set_schedule(self, schedule: int):
+        _check(lib().cavi_set_schedule(self.h, int(schedule)))
 
     def close(self):
         if self.h:
@@ -318,6 +336,12 @@ class CaviBatch:
 
     def sweep(self, n: int):
         _check(lib().cavi_batch_sweep(self.h, int(n)))
+
+    def schedule(self):
+        return _get_schedule(lib().cavi_batch_get_schedule, self.h)
+
+    def set_schedule(self, schedule: int):
+        _check(lib().cavi_batch_set_schedule(self.h, int(schedule)))
 
     def run(self, max_sweeps: int = 10000, rel_tol: float = 1e-6):
         """Returns ``(sweeps[B], elbo[B], n_converged)``."""

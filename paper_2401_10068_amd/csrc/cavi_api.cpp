@@ -41,6 +41,7 @@ cavi_status fail(cavi_status st, const char *fmt, ...)
     } while (0)
 
 constexpr int kGraphSweeps = 16;  // sweeps per captured graph
+constexpr int kTuneChunks = 2048; // the autotuner times the E-step on at most this many chunks
 constexpr int kHistSingle = 4096; // bounds kept by a single-dataset handle
 
 
@@ -60,6 +61,8 @@ struct Handle {
     hipGraphExec_t graph = nullptr;
     Ctl *hctl = nullptr;        // pinned host mirror of the control blocks
     int32_t *hcount = nullptr;  // pinned
+    bool tuned = false;         // E-step schedule chosen (autotuned or set)
+    float sched_ms[2] = {0.f, 0.f};
 };
 
 cavi_status make_shape(int32_t B, const int64_t *N, const int32_t *K, int32_t G, int hist_cap, Shape &s,
@@ -269,6 +272,59 @@ cavi_status enqueue_sweeps(Handle *c, int n)
     return CAVI_OK;
 }
 
+// Average duration (ms) of reps E-step launches with the handle's current schedule.  The
+// E-step writes only the chunk partials, which the next sweep overwrites.
+cavi_status time_estep(Handle *h, int reps, float *ms, int max_chunks = 0)
+{
+    Shape sh = h->s;
+    if (max_chunks > 0 && sh.nchunk > max_chunks) sh.nchunk = max_chunks;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(launch_ctl_begin(h->s, h->b, 1, 0, 0.0, 0, h->stream));
+    HIPCHK(hipEventRecord(e0, h->stream));
+    for (int i = 0; i < reps; ++i) HIPCHK(launch_estep_stats(sh, h->b, 0, h->stream));
+    HIPCHK(hipEventRecord(e1, h->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(launch_ctl_begin(h->s, h->b, 0, 0, 0.0, 0, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    *ms = t / (float)reps;
+    return CAVI_OK;
+}
+
+// Autotuner: the tiled E-step has two schedules with identical results (register-heavy:
+// unrolled exact terms, centres and responsibilities in registers; register-light: the same
+// values kept in LDS, more waves per SIMD).  Which is faster depends on G, K and the LDS the
+// tile takes, so both are timed on the handle's own data (its first kTuneChunks chunks, after
+// one warm-up launch each) at the first sweep or run, before that call sets the control
+// blocks and before the sweep graph is captured.
+cavi_status autotune(Handle *h)
+{
+    if (h->tuned) return CAVI_OK;
+    h->tuned = true;
+    if (!tiled_supported(h->s.Kmax, h->s.G)) return CAVI_OK;
+    float best = 0.f;
+    int pick = 0;
+    for (int v = 0; v < 2; ++v) {
+        h->s.schedule = v;
+        float warm = 0.f, t = 0.f;
+        cavi_status rs = time_estep(h, 1, &warm, kTuneChunks);
+        if (rs == CAVI_OK) rs = time_estep(h, 3, &t, kTuneChunks);
+        if (rs != CAVI_OK) return rs;
+        h->sched_ms[v] = t;
+        if (v == 0 || t < best) {
+            best = t;
+            pick = v;
+        }
+    }
+    h->s.schedule = pick;
+    return CAVI_OK;
+}
+
 cavi_status ensure_graph(Handle *c)
 {
     if (c->graph) return CAVI_OK;
@@ -316,6 +372,7 @@ cavi_status sweep_n(Handle *h, int32_t n, double *elbo_host)
     if (n < 0) return fail(CAVI_E_INVAL, "n=%d < 0", n);
     if (!all_have_state(h)) return fail(CAVI_E_STATE, "no state: call init_standard or set_state");
     cavi_status rs = refresh_coef(h);
+    if (rs == CAVI_OK) rs = autotune(h);  // before the control blocks are set for this call
     if (rs != CAVI_OK) return rs;
     const int cap = h->s.hist_cap;
     int done = 0;
@@ -342,6 +399,7 @@ cavi_status run_all(Handle *h, int32_t max_sweeps, double rel_tol)
     if (!(rel_tol >= 0.0) || !isfinite(rel_tol)) return fail(CAVI_E_INVAL, "rel_tol must be finite and >= 0");
     if (!all_have_state(h)) return fail(CAVI_E_STATE, "no state: call init_standard or set_state");
     cavi_status rs = refresh_coef(h);
+    if (rs == CAVI_OK) rs = autotune(h);  // before the control blocks are set for this call
     if (rs != CAVI_OK) return rs;
     HIPCHK(launch_ctl_begin(h->s, h->b, max_sweeps, 1, rel_tol, 0, h->stream));
     int issued = 0;
@@ -494,23 +552,60 @@ cavi_status cavi_profile_estep(cavi_ctx *ctx, int32_t reps, float *avg_ms)
     Handle *h = &ctx->h;
     if (!all_have_state(h)) return fail(CAVI_E_STATE, "no state: call cavi_init_standard or cavi_set_state");
     cavi_status rs = refresh_coef(h);
+    if (rs == CAVI_OK) rs = autotune(h);
     if (rs != CAVI_OK) return rs;
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    HIPCHK(launch_ctl_begin(h->s, h->b, 1, 0, 0.0, 0, h->stream));
-    HIPCHK(hipEventRecord(e0, h->stream));
-    for (int i = 0; i < reps; ++i) HIPCHK(launch_estep_stats(h->s, h->b, 0, h->stream));
-    HIPCHK(hipEventRecord(e1, h->stream));
-    HIPCHK(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    HIPCHK(launch_ctl_begin(h->s, h->b, 0, 0, 0.0, 0, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
-    *avg_ms = ms / (float)reps;
+    return time_estep(h, reps, avg_ms);
+}
+
+static cavi_status get_schedule(Handle *h, int32_t *schedule, float *ms)
+{
+    if (schedule) *schedule = h->s.schedule;
+    if (ms) {
+        ms[0] = h->sched_ms[0];
+        ms[1] = h->sched_ms[1];
+    }
     return CAVI_OK;
+}
+
+static cavi_status set_schedule(Handle *h, int32_t schedule)
+{
+    if (schedule < -1 || schedule > 1) return fail(CAVI_E_INVAL, "schedule=%d outside [-1, 1]", schedule);
+    if (h->graph) {
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    if (schedule == -1) {
+        h->tuned = false;
+        h->s.schedule = 0;
+    } else {
+        h->tuned = true;
+        h->s.schedule = schedule;
+    }
+    return CAVI_OK;
+}
+
+cavi_status cavi_get_schedule(cavi_ctx *ctx, int32_t *schedule, float *ms)
+{
+    if (!ctx) return fail(CAVI_E_INVAL, "ctx is NULL");
+    return get_schedule(&ctx->h, schedule, ms);
+}
+
+cavi_status cavi_set_schedule(cavi_ctx *ctx, int32_t schedule)
+{
+    if (!ctx) return fail(CAVI_E_INVAL, "ctx is NULL");
+    return set_schedule(&ctx->h, schedule);
+}
+
+cavi_status cavi_batch_get_schedule(cavi_batch *bt, int32_t *schedule, float *ms)
+{
+    if (!bt) return fail(CAVI_E_INVAL, "batch is NULL");
+    return get_schedule(&bt->h, schedule, ms);
+}
+
+cavi_status cavi_batch_set_schedule(cavi_batch *bt, int32_t schedule)
+{
+    if (!bt) return fail(CAVI_E_INVAL, "batch is NULL");
+    return set_schedule(&bt->h, schedule);
 }
 
 cavi_status cavi_get_responsibilities(cavi_ctx *ctx, float *r_dev)

@@ -58,6 +58,7 @@ struct Shape {
     int32_t nchunk;     // chunks of all datasets
     int32_t tile_rows;  // rows per LDS tile of the generic kernel
     int32_t hist_cap;   // bounds kept per dataset
+    int32_t schedule;   // tiled E-step schedule: 0 register-heavy, 1 register-light (autotuned)
     int64_t Ntot;       // rows of all datasets
     int64_t Nmax;       // rows of the largest dataset
 };

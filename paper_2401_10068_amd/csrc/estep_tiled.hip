@@ -55,7 +55,7 @@ struct Cfg {
     static constexpr int LOADS = G / 8;                  // 16-byte loads per lane per 32-row slab
     static constexpr int GB = G < 16 ? G : 16;           // screened genes
     static constexpr int HG = (G - GB) / 2;              // remaining genes per half row
-    static constexpr int LDS_BYTES = (kT * XS + kT * LS + KT * PS + KT) * 4;
+    static constexpr int LDS_BYTES = (kT * XS + kT * LS + KT * PS + KT + KT * G) * 4;
     static_assert(G % 4 == 0 && HG % 4 == 0, "gene blocks of 4");
     static_assert(G % 8 == 0, "a slab must split evenly into 16-byte loads");
     static_assert(8 * KT * G <= kT * XS, "per-wave sums must fit the x tile");
@@ -65,14 +65,18 @@ struct Cfg {
 // One wave's 32-row slab of a tile: G/8 16-byte loads per lane, coalesced along the rows.
 // Rows past the end of a ragged slab re-read its last row: the loads stay unconditional, so
 // the compiler keeps all of them in flight at once.
-template <int G>
+template <int G, bool OPAQUE>
 __device__ __forceinline__ void load_slab(f4 (&pre)[G / 8], const float *__restrict__ x, int64_t row0, int nr,
                                           int lane)
 {
     constexpr int C4 = G / 4;
+    // OPAQUE: an opaque copy of the lane index, so that the offsets below are recomputed at
+    // every call instead of being hoisted out of the tile loop and held for its duration
+    int ln = lane;
+    if (OPAQUE) asm volatile("" : "+v"(ln));
 #pragma unroll
     for (int j = 0; j < G / 8; ++j) {
-        const int i = lane + j * 64;
+        const int i = ln + j * 64;
         const int row = i / C4;
         const int col = (i - row * C4) * 4;
         const int rr = row < nr ? row : nr - 1;
@@ -80,26 +84,28 @@ __device__ __forceinline__ void load_slab(f4 (&pre)[G / 8], const float *__restr
     }
 }
 
-template <int G>
+template <int G, bool OPAQUE>
 __device__ __forceinline__ void store_slab(const f4 (&pre)[G / 8], float *xs, int nr, int lane)
 {
     constexpr int C4 = G / 4, XS = G + 4;
+    int ln = lane;
+    if (OPAQUE) asm volatile("" : "+v"(ln));
 #pragma unroll
     for (int j = 0; j < G / 8; ++j) {
-        const int i = lane + j * 64;
+        const int i = ln + j * 64;
         const int row = i / C4;
         const int col = (i - row * C4) * 4;
         if (row < nr) *(f4 *)(xs + row * XS + col) = pre[j];
     }
 }
 
-// sum over N genes from g0 of (h x + q)^2, x from an LDS row, (h, q) from an LDS table row
-template <int N>
+// sum over N genes from g0 of (h x + q)^2, x from an LDS row, (h, q) from an LDS table row;
+// UNROLL: all loads issued up front (more registers) or one block of 4 genes at a time
+template <int N, bool UNROLL>
 __device__ __forceinline__ float tail_sum(const float *xr, const float *pr, int g0)
 {
     float s = 0.f;
-#pragma unroll
-    for (int g = 0; g < N; g += 4) {
+    auto step = [&](int g) {
         const f4 xv = *(const f4 *)(xr + g0 + g);
         const f4 p0 = *(const f4 *)(pr + 2 * (g0 + g));
         const f4 p1 = *(const f4 *)(pr + 2 * (g0 + g) + 4);
@@ -108,6 +114,13 @@ __device__ __forceinline__ float tail_sum(const float *xr, const float *pr, int 
         u = fmaf(xv.y, p0.z, p0.w); s = fmaf(u, u, s);
         u = fmaf(xv.z, p1.x, p1.y); s = fmaf(u, u, s);
         u = fmaf(xv.w, p1.z, p1.w); s = fmaf(u, u, s);
+    };
+    if (UNROLL) {
+#pragma unroll
+        for (int g = 0; g < N; g += 4) step(g);
+    } else {
+#pragma unroll 1
+        for (int g = 0; g < N; g += 4) step(g);
     }
     return s;
 }
@@ -148,7 +161,7 @@ __device__ __forceinline__ double wave_sum(double v)
 
 }  // namespace
 
-template <int KT, int G, bool INIT>
+template <int KT, int G, bool INIT, bool LOWREG>
 __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
 {
     using C = Cfg<KT, G>;
@@ -158,6 +171,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
     float *ls = xs + kT * XS;         // kT x LS   partial, then exact, row log-likelihood sums
     float *pt = ls + kT * LS;         // KT x PS   (h, q) table
     float *ccs = pt + KT * PS;        // KT        c_k
+    float *mft = ccs + KT;            // KT x G   FP32 centres of the statistics
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -177,7 +191,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
         f4 pre[C::LOADS];
         {
             const int nj0 = min(32, min(kT, nrc) - jbase);
-            if (nj0 > 0) load_slab<G>(pre, x, r0 + jbase, nj0, lane);
+            if (nj0 > 0) load_slab<G, LOWREG>(pre, x, r0 + jbase, nj0, lane);
         }
         const size_t kb = (size_t)bi * s.Kmax;
         const float *__restrict__ cc = bf.cc + kb;
@@ -189,20 +203,23 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
         // coefficients: every load unconditional (indexes clamped into the dataset's arrays),
         // then one wait, so that no load of the tile loop's prefetch is ever waited on early
         constexpr int NPT = (KT * G + kBlock - 1) / kBlock;
-        float hv[NPT], qv[NPT];
+        float hv[NPT], qv[NPT], mv[NPT];
 #pragma unroll
         for (int u = 0; u < NPT; ++u) {
             const int ic = min(tid + u * kBlock, KG - 1);
             // initialisation: the table holds the seed rows instead of (h, q)
             hv[u] = INIT ? seedp[ic] : hq[2 * ic];
             qv[u] = INIT ? 0.f : hq[2 * ic + 1];
+            mv[u] = mf[ic];
         }
         const float ccv = cc[min(tid, K - 1)];
-        float mfv[KT][GS];
+        // register-heavy schedule: the centres stay in registers for the whole chunk
+        float mfr[KT][GS];
 #pragma unroll
         for (int k = 0; k < KT; ++k)
 #pragma unroll
-            for (int sl = 0; sl < GS; ++sl) mfv[k][sl] = mf[min(k, K - 1) * G + min(lane + 64 * sl, G - 1)];
+            for (int sl = 0; sl < GS; ++sl)
+                mfr[k][sl] = LOWREG ? 0.f : mf[min(k, K - 1) * G + min(lane + 64 * sl, G - 1)];
         __builtin_amdgcn_s_waitcnt(kWaitVm0);
 #pragma unroll
         for (int u = 0; u < NPT; ++u) {
@@ -211,15 +228,16 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
                 const int k = i / G, g = i - k * G;
                 pt[k * PS + 2 * g] = k < K ? hv[u] : 0.f;
                 pt[k * PS + 2 * g + 1] = k < K ? qv[u] : 0.f;
+                mft[i] = k < K ? mv[u] : 0.f;
             }
         }
         if (tid < KT) ccs[tid] = tid < K ? ccv : 0.f;
+        lds_barrier();  // the coefficient tables are complete
 #pragma unroll
         for (int k = 0; k < KT; ++k)
 #pragma unroll
             for (int sl = 0; sl < GS; ++sl)
-                if (k >= K || lane + 64 * sl >= G) mfv[k][sl] = 0.f;
-        lds_barrier();  // the coefficient table is complete
+                if (k >= K || lane + 64 * sl >= G) mfr[k][sl] = 0.f;
 
         float t0[KT], t1[KT][GS], t2[KT][GS];
 #pragma unroll
@@ -235,10 +253,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
             const int nj = max(0, min(32, nr - jbase));
             // each wave stages, screens, sums and accumulates its own 32 rows: no workgroup
             // barrier inside the tile loop
-            if (nj > 0) store_slab<G>(pre, xs + jbase * XS, nj, lane);
+            if (nj > 0) store_slab<G, LOWREG>(pre, xs + jbase * XS, nj, lane);
             if (t + 1 < ntiles) {
                 const int nj1 = min(32, min(kT, nrc - (t + 1) * kT) - jbase);
-                if (nj1 > 0) load_slab<G>(pre, x, r0 + (int64_t)(t + 1) * kT + jbase, nj1, lane);
+                if (nj1 > 0) load_slab<G, LOWREG>(pre, x, r0 + (int64_t)(t + 1) * kT + jbase, nj1, lane);
             }
             wave_lds_sync();
             if (nj == 0) continue;
@@ -329,7 +347,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
                 }
                 // exact l for the best-bounded subpopulation
                 const float pkh = lr[kh];
-                const float sh = act ? tail_sum<HG>(xr, pt + kh * PS, GB + half * HG) : 0.f;
+                const float sh = act ? tail_sum<HG, !LOWREG>(xr, pt + kh * PS, GB + half * HG) : 0.f;
                 const float so = __shfl_xor(sh, 32, 64);
                 const float lkh = ccs[kh] - (pkh + (half == 0 ? sh + so : so + sh));
                 uint32_t cm = 0;
@@ -345,7 +363,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
                     const bool mine = cm != 0;
                     const int k = mine ? __builtin_ctz(cm) : 0;
                     const float pk = lr[k];
-                    const float sk = mine ? tail_sum<HG>(xr, pt + k * PS, GB + half * HG) : 0.f;
+                    const float sk = mine ? tail_sum<HG, !LOWREG>(xr, pt + k * PS, GB + half * HG) : 0.f;
                     const float sko = __shfl_xor(sk, 32, 64);
                     __builtin_amdgcn_wave_barrier();
                     if (mine) {
@@ -395,7 +413,15 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
                     if (rone == 1.f) mk |= kOneHot;
                 }
                 hacc += (double)h;
+                if (LOWREG) {
+                    // the responsibilities replace the row's l values in LDS for the statistics
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                    for (int k = 0; k < KT; ++k)
+                        if (k < K) lr[k] = rv[k];
+                }
             }
+            if (LOWREG) wave_lds_sync();
 
             }  // phases A, B and log-sum-exp
 
@@ -405,20 +431,33 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
             //    exactly 1 skip the multiplication.
             if (nj > 0) {
                 const bool own = act && half == 0;
+                // per-slot gene of this lane, as an opaque value: the LDS addresses below are
+                // formed from it here rather than hoisted out of the tile loop and held
+                int gl[GS];
+#pragma unroll
+                for (int sl = 0; sl < GS; ++sl) {
+                    gl[sl] = min(lane + 64 * sl, G - 1);
+                    if (LOWREG) asm volatile("" : "+v"(gl[sl]));
+                }
 #pragma unroll
                 for (int k = 0; k < KT; ++k) {
                     if (k >= K) break;
                     const bool nzk = own && (mk & (1u << k));
                     uint64_t one = __ballot(nzk && (mk & kOneHot));
                     uint64_t soft = __ballot(nzk && !(mk & kOneHot));
+                    if (LOWREG && !(one | soft)) continue;
+                    float mfv[GS];
+#pragma unroll
+                    for (int sl = 0; sl < GS; ++sl) mfv[sl] = LOWREG ? mft[k * G + gl[sl]] : mfr[k][sl];
                     while (one) {
                         const int jj = __builtin_ctzll(one);
                         one &= one - 1;
 #pragma unroll
                         for (int sl = 0; sl < GS; ++sl) {
                             const int g = lane + 64 * sl;
-                            const float xv = (g < G) ? xs[(jbase + jj) * XS + g] : 0.f;
-                            const float d = xv - mfv[k][sl];
+                            const float xv = LOWREG ? xs[(jbase + jj) * XS + gl[sl]]
+                                                    : ((g < G) ? xs[(jbase + jj) * XS + g] : 0.f);
+                            const float d = xv - mfv[sl];
                             t1[k][sl] += d;
                             t2[k][sl] = fmaf(d, d, t2[k][sl]);
                         }
@@ -426,12 +465,14 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
                     while (soft) {
                         const int jj = __builtin_ctzll(soft);
                         soft &= soft - 1;
-                        const float r = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rv[k]), jj));
+                        const float r = LOWREG ? ls[(jbase + jj) * LS + k]
+                                               : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rv[k]), jj));
 #pragma unroll
                         for (int sl = 0; sl < GS; ++sl) {
                             const int g = lane + 64 * sl;
-                            const float xv = (g < G) ? xs[(jbase + jj) * XS + g] : 0.f;
-                            const float d = xv - mfv[k][sl];
+                            const float xv = LOWREG ? xs[(jbase + jj) * XS + gl[sl]]
+                                                    : ((g < G) ? xs[(jbase + jj) * XS + g] : 0.f);
+                            const float d = xv - mfv[sl];
                             const float wv = r * d;
                             t1[k][sl] += wv;
                             t2[k][sl] = fmaf(wv, d, t2[k][sl]);
@@ -489,9 +530,11 @@ hipError_t launch_t(const Shape &s, const Bufs &b, int init_mode, hipStream_t st
 {
     constexpr int lds = Cfg<KT, G>::LDS_BYTES;
     if (init_mode)
-        hipLaunchKernelGGL((k_estep_tiled<KT, G, true>), dim3(s.nchunk), dim3(kBlock), lds, st, s, b);
+        hipLaunchKernelGGL((k_estep_tiled<KT, G, true, true>), dim3(s.nchunk), dim3(kBlock), lds, st, s, b);
+    else if (s.schedule == 1)
+        hipLaunchKernelGGL((k_estep_tiled<KT, G, false, true>), dim3(s.nchunk), dim3(kBlock), lds, st, s, b);
     else
-        hipLaunchKernelGGL((k_estep_tiled<KT, G, false>), dim3(s.nchunk), dim3(kBlock), lds, st, s, b);
+        hipLaunchKernelGGL((k_estep_tiled<KT, G, false, false>), dim3(s.nchunk), dim3(kBlock), lds, st, s, b);
     return hipGetLastError();
 }
 

@@ -288,3 +288,31 @@ def test_error_paths(torch_cuda):
     cx.close()
     for a, b in zip(g, st0.arrays()):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("N,K,G", [(9000, 8, 96), (5000, 16, 48), (3000, 3, 16), (2100, 5, 128)])
+def test_schedules_bitwise_equal_and_autotuned(torch_cuda, N, K, G):
+    """The autotuner's two E-step schedules give bitwise the same states and bounds, and the
+    tuner times both and keeps one of them."""
+    X = overlapping(31, N, K, G)
+    m0 = oc.data_mean(X)
+    st0 = oc.init_standard(X, K, oc.Prior(), m0, seed=5)
+    results = []
+    for sched in (0, 1):
+        cx = gpu_ctx(torch_cuda, X, K, m0)
+        cx.set_state(*st0.arrays())
+        cx.set_schedule(sched)
+        el = cx.sweep(20)
+        results.append((el, cx.get_state()))
+        assert cx.schedule()[0] == sched
+        cx.close()
+    np.testing.assert_array_equal(results[0][0], results[1][0])
+    for a, b in zip(results[0][1], results[1][1]):
+        np.testing.assert_array_equal(a, b)
+    cx = gpu_ctx(torch_cuda, X, K, m0)
+    cx.set_state(*st0.arrays())
+    el = cx.sweep(20)
+    pick, ms = cx.schedule()
+    assert pick in (0, 1) and ms[0] > 0 and ms[1] > 0
+    np.testing.assert_array_equal(el, results[0][0])
+    cx.close()
