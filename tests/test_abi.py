@@ -78,3 +78,28 @@ def test_null_handles(L):
     assert L.cavi_run(None, 10, 1e-6, None, None) == cavi.CAVI_E_INVAL
     assert L.cavi_get_state(None, None, None, None, None, None) == cavi.CAVI_E_INVAL
     assert L.cavi_init_standard(None, 0) == cavi.CAVI_E_INVAL
+
+
+def test_warm_start_and_schedule_entry_points_reject_bad_arguments(L):
+    """Host-side checks of the warm-start and schedule entry points (no device is touched)."""
+    h = C.c_void_p()
+    for dims in [(0, 8, 1, 4, 8), (4, 8, -1, 4, 8), (4, 8, 1, 0, 8), (4, 8, 1, 4, 0)]:
+        assert L.cavi_mlp_create(C.byref(h), *dims, C.c_uint64(0), None) == cavi.CAVI_E_INVAL
+    assert L.cavi_mlp_create(None, 4, 8, 1, 4, 8, C.c_uint64(0), None) == cavi.CAVI_E_INVAL
+    assert L.cavi_mlp_destroy(None) == cavi.CAVI_OK
+    assert L.cavi_mlp_forward(None, None, 1, None) == cavi.CAVI_E_INVAL
+    assert L.cavi_mlp_loss_grad(None, None, None, 1, None) == cavi.CAVI_E_INVAL
+    assert L.cavi_mlp_adamw(None, 1e-3, 0.9, 0.999, 1e-8, 0.0) == cavi.CAVI_E_INVAL
+    n = C.c_int64(0)
+    assert L.cavi_mlp_n_params(None, C.byref(n)) == cavi.CAVI_E_INVAL
+    assert L.cavi_features(None, None, 1, 4, None, None) == cavi.CAVI_E_INVAL
+    assert L.cavi_features(C.c_void_p(0x1000), C.c_void_p(0x2000), 0, 4, C.c_void_p(0x3000), None) == cavi.CAVI_E_INVAL
+    assert L.cavi_features(C.c_void_p(0x1000), C.c_void_p(0x2000), 2, 513, C.c_void_p(0x3000), None) == cavi.CAVI_E_INVAL
+    assert L.cavi_warm_targets(None, None, None, 1, 8, 48, None, None) == cavi.CAVI_E_INVAL
+    p = C.c_void_p(0x1000)
+    assert L.cavi_warm_targets(p, p, p, 1, 65, 48, p, None) == cavi.CAVI_E_INVAL
+    assert L.cavi_batch_set_state_warm(None, None, 10) == cavi.CAVI_E_INVAL
+    assert L.cavi_set_schedule(None, 0) == cavi.CAVI_E_INVAL
+    assert L.cavi_get_schedule(None, None, None) == cavi.CAVI_E_INVAL
+    assert L.cavi_batch_set_schedule(None, 1) == cavi.CAVI_E_INVAL
+    assert L.cavi_batch_get_schedule(None, None, None) == cavi.CAVI_E_INVAL
