@@ -26,7 +26,11 @@
  *   - State arrays passed to set/get are HOST memory, FP64, caller-owned:
  *     alpha[K], and m, beta, a, b as K x G arrays, k-major (index k*G + g).
  *   - All work is enqueued on the stream given at creation (a hipStream_t
- *     passed as void*, NULL = the default stream).  Functions that return
+ *     passed as void*).  NULL: the handle creates a blocking stream of its
+ *     own (sweeps are captured into a hipGraph, which the default stream
+ *     cannot hold); work on the default stream is then ordered before and
+ *     after the handle's work, work on other streams is not and must be
+ *     synchronised by the caller.  Functions that return
  *     results to the host (get_*, sweep with an ELBO buffer, run) synchronise
  *     that stream.  A handle is not thread-safe.
  *   - Workspace: pass device memory of at least cavi_workspace_bytes() bytes
@@ -170,7 +174,9 @@ cavi_status cavi_batch_set_state(cavi_batch *bt, int32_t b, const double *alpha,
  * alpha_k = alpha0 + n_k, beta = beta0 + n_k, m = mu, a = a0 + n_k / 2,
  * b = a / E[tau] (ln E[tau] clamped to [-30, 30]).  The paper has no warm
  * start: this only chooses the starting point of the coordinate updates of
- * Section 3.4, which then run as from any set state.  Synchronises the
+ * Section 3.4, which then run as from any set state.  out_dev must be
+ * complete when the handle's stream reaches this call (written on that
+ * stream or on the default stream, or synchronised).  Synchronises the
  * stream. */
 cavi_status cavi_batch_set_state_warm(cavi_batch *bt, const float *out_dev, int32_t ld);
 
@@ -224,8 +230,9 @@ cavi_status cavi_batch_destroy(cavi_batch *bt);
  *              moments, step count kept by the handle).
  *   get/set_params, get_grads: HOST FP32 arrays of n_params entries
  *              (synchronise).
- * B <= max_batch.  Work is enqueued on hip_stream (NULL: a stream the
- * handle creates).  Not thread-safe.
+ * B <= max_batch.  Work is enqueued on hip_stream (NULL: the default
+ * stream, so that outputs are ordered before a CAVI handle's later work).
+ * Not thread-safe.
  * ------------------------------------------------------------------------ */
 cavi_status cavi_features(const float *x_dev, const int64_t *row_off_dev, int32_t B, int32_t G,
                           float *feat_dev, void *hip_stream);

@@ -128,12 +128,9 @@ cavi_status cavi_mlp_create(cavi_mlp **out, int32_t in_dim, int32_t hidden, int3
         }
     }
     hipError_t e = hipSuccess;
-    if (hip_stream) {
-        n->stream = (hipStream_t)hip_stream;
-    } else {
-        e = hipStreamCreate(&n->stream);
-        n->own_stream = true;
-    }
+    // NULL: the default stream, which orders the network's work with the caller's default-stream
+    // work and with the CAVI handles' own streams (they are blocking streams)
+    n->stream = (hipStream_t)hip_stream;
     const size_t pb = sizeof(float) * n->nparams;
     if (e == hipSuccess) e = hipMalloc(&n->params, pb);
     if (e == hipSuccess) e = hipMalloc(&n->grads, pb);
