@@ -13,7 +13,7 @@ namespace {
 
 constexpr double kLn2Pi = 1.8378770664093454835606594728112;
 constexpr double kTwoPi = 6.283185307179586476925286766559;
-constexpr int kRedBlock = 1024;  // k_reduce: 16 waves per 16 statistics
+constexpr int kRedBlock = 1024;  // k_reduce: 16 waves per 64 statistics
 constexpr int kMBlock = 1024;    // k_mstep, k_coef: one (k, g) item per thread up to K G = 1024
 
 // Sum over the 64 lanes of a wave with a fixed butterfly (same order every run).
@@ -108,34 +108,39 @@ __device__ __forceinline__ void coef_rows(const View &v, MShared &sh, const Prio
 }  // namespace
 
 // totals[b][i] = sum over the chunks of dataset b of partials[chunk][i], in a
-// fixed order.  A workgroup takes 16 statistics; wave v sums a contiguous 1/16 of the
-// chunks, lane (q, i) of it every fourth chunk from the q-th, then the four lane sums are
-// added in q order and the 16 wave sums in wave order.
+// fixed order: wave v of the block sums a contiguous 1/16 of the chunks (4
+// interleaved accumulators), then the 16 wave sums are added in wave order.
 __global__ __launch_bounds__(kRedBlock) void k_reduce(Shape s, Bufs bf, int init_mode)
 {
     const int bi = blockIdx.y;
     if (!init_mode && sweep_skipped(bf.ctl + bi)) return;
     const Ds d = bf.ds[bi];
     const int S = d.K + 2 * d.K * s.G + 1;
-    __shared__ double part[kRedBlock / 64][16];
+    __shared__ double part[kRedBlock / 64][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int nw = kRedBlock / 64;
-    const int li = lane & 15, q = lane >> 4;
-    const int i = blockIdx.x * 16 + li;
-    if (blockIdx.x * 16 >= S) return;
+    const int i = blockIdx.x * 64 + lane;
+    if (blockIdx.x * 64 >= S) return;
     const double *pp = bf.partials + (size_t)d.chunk0 * s.Smax;
     double acc = 0.0;
     if (i < S) {
         const int c0 = (int)(((int64_t)d.nchunk * wv) / nw), c1 = (int)(((int64_t)d.nchunk * (wv + 1)) / nw);
-        for (int c = c0 + q; c < c1; c += 4) acc += pp[(size_t)c * s.Smax + i];
+        double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+        int c = c0;
+        for (; c + 4 <= c1; c += 4) {
+            q0 += pp[(size_t)c * s.Smax + i];
+            q1 += pp[(size_t)(c + 1) * s.Smax + i];
+            q2 += pp[(size_t)(c + 2) * s.Smax + i];
+            q3 += pp[(size_t)(c + 3) * s.Smax + i];
+        }
+        for (; c < c1; ++c) q0 += pp[(size_t)c * s.Smax + i];
+        acc = (q0 + q1) + (q2 + q3);
     }
-    // lanes li, li+16, li+32, li+48 hold q = 0..3: add them in q order
-    const double a1 = __shfl(acc, li + 16, 64), a2 = __shfl(acc, li + 32, 64), a3 = __shfl(acc, li + 48, 64);
-    if (q == 0) part[wv][li] = ((acc + a1) + a2) + a3;
+    part[wv][lane] = acc;
     __syncthreads();
-    if (wv == 0 && q == 0 && i < S) {
-        double t = part[0][li];
-        for (int v = 1; v < nw; ++v) t += part[v][li];
+    if (wv == 0 && i < S) {
+        double t = part[0][lane];
+        for (int v = 1; v < nw; ++v) t += part[v][lane];
         bf.totals[(size_t)bi * s.Smax + i] = t;
     }
 }
@@ -281,7 +286,7 @@ __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, in
 
 hipError_t launch_reduce(const Shape &s, const Bufs &b, int init_mode, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce, dim3((s.Smax + 15) / 16, s.B), dim3(kRedBlock), 0, st, s, b, init_mode);
+    hipLaunchKernelGGL(k_reduce, dim3((s.Smax + 63) / 64, s.B), dim3(kRedBlock), 0, st, s, b, init_mode);
     return hipGetLastError();
 }
 
