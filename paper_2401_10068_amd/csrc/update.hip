@@ -25,7 +25,7 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 struct MShared {
-    double red[kMBlock];
+    double red[kMBlock / 64];
     double ak[kMaxK], psi_ak[kMaxK], lg_ak[kMaxK], term_k[kMaxK];
     double tmp[kMaxKG];
     double asum, psum;
@@ -196,7 +196,13 @@ __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, in
     const double prior_const = half_ln_b0 + p.a0 * log(p.b0) - dev_lgamma(p.a0);
     double acc = 0.0;
     int bad = 0;
-    for (int q = tid; q < KG; q += kMBlock) {
+    // the new state of this thread's items stays in registers until the commit
+    constexpr int kItems = kMaxKG / kMBlock;
+    double nmv[kItems], nbt[kItems], nav[kItems], nbv[kItems];
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const int q = tid + it * kMBlock;
+        if (q >= KG) break;
         const int k = q / G, g = q - k * G;
         const double Nk = T0[k];
         const double c = (double)v.mf[q];
@@ -207,10 +213,10 @@ __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, in
         const double aa = p.a0 + 0.5 * Nk;
         double bb = p.b0 + 0.5 * (T2[q] + p.beta0 * m0p * m0p - bt * mp * mp);
         if (bb < p.b0) bb = p.b0;
-        v.nm[q] = mm;
-        v.nbeta[q] = bt;
-        v.na[q] = aa;
-        v.nb[q] = bb;
+        nmv[it] = mm;
+        nbt[it] = bt;
+        nav[it] = aa;
+        nbv[it] = bb;
         const double elt = dev_digamma(aa) - log(bb);
         const double tb = aa / bb;
         if (!init_mode) {
@@ -238,10 +244,12 @@ __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, in
     }
     __syncthreads();
     coef_rows(v, sh, &p, !init_mode);
-    sh.red[tid] = acc;
-    __syncthreads();
-    for (int off = kMBlock / 2; off > 0; off >>= 1) {
-        if (tid < off) sh.red[tid] += sh.red[tid + off];
+    {
+        const double ws = wave_sum(acc);
+        if ((tid & 63) == 0) sh.red[tid >> 6] = ws;
+        __syncthreads();
+        if (tid == 0)
+            for (int w = 1; w < kMBlock / 64; ++w) sh.red[0] += sh.red[w];
         __syncthreads();
     }
     if (tid == 0) {
@@ -276,11 +284,14 @@ __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, in
     __syncthreads();
     if (sh.bad) return;
     if (tid < K) v.alpha[tid] = v.nalpha[tid];
-    for (int q = tid; q < KG; q += kMBlock) {
-        v.m[q] = v.nm[q];
-        v.beta[q] = v.nbeta[q];
-        v.a[q] = v.na[q];
-        v.b[q] = v.nb[q];
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const int q = tid + it * kMBlock;
+        if (q >= KG) break;
+        v.m[q] = nmv[it];
+        v.beta[q] = nbt[it];
+        v.a[q] = nav[it];
+        v.b[q] = nbv[it];
     }
 }
 
