@@ -51,11 +51,15 @@ struct Cfg {
     static constexpr int LS = (KT == 4) ? 12 : KT + 4;   // LDS row stride of the partial / exact l
     static constexpr int PS = 2 * G + 4;                 // LDS row stride of the (h, q) table
     static constexpr int KH = KT / 2;                    // subpopulations per lane (screen)
-    static constexpr int GS = (G + 63) / 64;             // gene slots per lane (statistics)
+    static constexpr int GS = (G + 63) / 64;             // genes per lane (statistics): GS l .. GS l + GS - 1
     static constexpr int LOADS = G / 8;                  // 16-byte loads per lane per 32-row slab
     static constexpr int GB = G < 16 ? G : 16;           // screened genes
     static constexpr int HG = (G - GB) / 2;              // remaining genes per half row
     static constexpr int LDS_BYTES = (kT * XS + kT * LS + KT * PS + KT + KT * G) * 4;
+    // waves per SIMD that the LDS allows (160 KB per CU, four waves per workgroup, one per
+    // SIMD), 2 or 3: the register-light schedule is built to fit that many (168 registers
+    // for 3; a budget of 128 for 4 would spill)
+    static constexpr int LDS_WAVES = (163840 / LDS_BYTES) >= 3 ? 3 : 2;
     static_assert(G % 4 == 0 && HG % 4 == 0, "gene blocks of 4");
     static_assert(G % 8 == 0, "a slab must split evenly into 16-byte loads");
     static_assert(8 * KT * G <= kT * XS, "per-wave sums must fit the x tile");
@@ -82,6 +86,28 @@ __device__ __forceinline__ void load_slab(f4 (&pre)[G / 8], const float *__restr
         const int rr = row < nr ? row : nr - 1;
         pre[j] = *(const f4 *)(x + (row0 + rr) * G + col);
     }
+}
+
+// the GS consecutive genes of a statistics lane from an LDS row (one 4- or 8-byte read)
+template <int GS>
+__device__ __forceinline__ void read_genes(float (&v)[GS], const float *p)
+{
+    static_assert(GS == 1 || GS == 2, "one or two genes per lane");
+    if constexpr (GS == 2) {
+        const float2 t = *(const float2 *)p;
+        v[0] = t.x;
+        v[1] = t.y;
+    } else {
+        v[0] = *p;
+    }
+}
+
+// the values are needed here: a read of them is not moved into a later conditional block
+template <int GS>
+__device__ __forceinline__ void keep(float (&v)[GS])
+{
+#pragma unroll
+    for (int i = 0; i < GS; ++i) asm volatile("" ::"v"(v[i]));
 }
 
 template <int G, bool OPAQUE>
@@ -162,7 +188,7 @@ __device__ __forceinline__ double wave_sum(double v)
 }  // namespace
 
 template <int KT, int G, bool INIT, bool LOWREG>
-__global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
+__global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void k_estep_tiled(Shape s, Bufs bf)
 {
     using C = Cfg<KT, G>;
     constexpr int XS = C::XS, LS = C::LS, PS = C::PS, KH = C::KH, GS = C::GS, GB = C::GB, HG = C::HG;
@@ -213,13 +239,17 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
             mv[u] = mf[ic];
         }
         const float ccv = cc[min(tid, K - 1)];
+        // statistics lanes: lane l owns genes GS l .. GS l + GS - 1 when GS l < G; the other
+        // lanes read gene 0 onwards instead and their sums are never written
+        const bool gown = GS * lane < G;
+        const int g0 = gown ? GS * lane : 0;
         // register-heavy schedule: the centres stay in registers for the whole chunk
         float mfr[KT][GS];
 #pragma unroll
         for (int k = 0; k < KT; ++k)
 #pragma unroll
             for (int sl = 0; sl < GS; ++sl)
-                mfr[k][sl] = LOWREG ? 0.f : mf[min(k, K - 1) * G + min(lane + 64 * sl, G - 1)];
+                mfr[k][sl] = LOWREG ? 0.f : mf[min(k, K - 1) * G + g0 + sl];
         __builtin_amdgcn_s_waitcnt(kWaitVm0);
 #pragma unroll
         for (int u = 0; u < NPT; ++u) {
@@ -237,7 +267,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
         for (int k = 0; k < KT; ++k)
 #pragma unroll
             for (int sl = 0; sl < GS; ++sl)
-                if (k >= K || lane + 64 * sl >= G) mfr[k][sl] = 0.f;
+                if (k >= K || !gown) mfr[k][sl] = 0.f;
 
         float t0[KT], t1[KT][GS], t2[KT][GS];
 #pragma unroll
@@ -426,57 +456,101 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
             }  // phases A, B and log-sum-exp
 
             // C. statistics over the same rows, lanes over genes.  For each subpopulation
-            //    (a static loop, so the sums stay in registers) walk the rows whose
-            //    responsibility for it is nonzero; rows with a single responsibility of
-            //    exactly 1 skip the multiplication.
+            //    walk the rows whose responsibility for it is nonzero, two rows per step so
+            //    that their LDS reads overlap; rows with a single responsibility of exactly 1
+            //    skip the multiplication.  Rows are added in increasing order (one-hot rows
+            //    first).  With KT = 16 the subpopulation loop is not unrolled, so the sums
+            //    cannot be indexed statically: the slab's rows are summed in two registers
+            //    and that sum is added to the wave's running sum; otherwise the rows are
+            //    added to the running sum directly.
             if (nj > 0) {
                 const bool own = act && half == 0;
-                // per-slot gene of this lane, as an opaque value: the LDS addresses below are
-                // formed from it here rather than hoisted out of the tile loop and held
-                int gl[GS];
-#pragma unroll
-                for (int sl = 0; sl < GS; ++sl) {
-                    gl[sl] = min(lane + 64 * sl, G - 1);
-                    if (LOWREG) asm volatile("" : "+v"(gl[sl]));
-                }
+                // the lane's first gene, as an opaque value in the register-light schedule: the
+                // LDS addresses below are formed from it here rather than hoisted out of the
+                // tile loop and held
+                int gq = g0;
+                if (LOWREG) asm volatile("" : "+v"(gq));
+                const float *xl = xs + jbase * XS + gq;
+                constexpr bool kSlabSums = KT > 8;
 #pragma unroll
                 for (int k = 0; k < KT; ++k) {
                     if (k >= K) break;
                     const bool nzk = own && (mk & (1u << k));
                     uint64_t one = __ballot(nzk && (mk & kOneHot));
                     uint64_t soft = __ballot(nzk && !(mk & kOneHot));
-                    if (LOWREG && !(one | soft)) continue;
-                    float mfv[GS];
+                    if (!(one | soft)) continue;
+                    float mfv[GS], u1[GS], u2[GS];
 #pragma unroll
-                    for (int sl = 0; sl < GS; ++sl) mfv[sl] = LOWREG ? mft[k * G + gl[sl]] : mfr[k][sl];
+                    for (int sl = 0; sl < GS; ++sl) {
+                        u1[sl] = kSlabSums ? 0.f : t1[k][sl];
+                        u2[sl] = kSlabSums ? 0.f : t2[k][sl];
+                    }
+                    if (LOWREG) {
+                        read_genes<GS>(mfv, mft + k * G + gq);
+                    } else {
+#pragma unroll
+                        for (int sl = 0; sl < GS; ++sl) mfv[sl] = mfr[k][sl];
+                    }
                     while (one) {
-                        const int jj = __builtin_ctzll(one);
+                        const int ja = __builtin_ctzll(one);
                         one &= one - 1;
+                        const bool two = one != 0;
+                        const int jb = two ? __builtin_ctzll(one) : ja;
+                        if (two) one &= one - 1;
+                        float xa[GS], xb[GS];
+                        read_genes<GS>(xa, xl + ja * XS);
+                        read_genes<GS>(xb, xl + jb * XS);
+                        keep<GS>(xb);  // both reads are issued before the branch below
 #pragma unroll
                         for (int sl = 0; sl < GS; ++sl) {
-                            const int g = lane + 64 * sl;
-                            const float xv = LOWREG ? xs[(jbase + jj) * XS + gl[sl]]
-                                                    : ((g < G) ? xs[(jbase + jj) * XS + g] : 0.f);
-                            const float d = xv - mfv[sl];
-                            t1[k][sl] += d;
-                            t2[k][sl] = fmaf(d, d, t2[k][sl]);
+                            const float d = xa[sl] - mfv[sl];
+                            u1[sl] += d;
+                            u2[sl] = fmaf(d, d, u2[sl]);
+                        }
+                        if (two) {
+#pragma unroll
+                            for (int sl = 0; sl < GS; ++sl) {
+                                const float d = xb[sl] - mfv[sl];
+                                u1[sl] += d;
+                                u2[sl] = fmaf(d, d, u2[sl]);
+                            }
                         }
                     }
                     while (soft) {
-                        const int jj = __builtin_ctzll(soft);
+                        const int ja = __builtin_ctzll(soft);
                         soft &= soft - 1;
-                        const float r = LOWREG ? ls[(jbase + jj) * LS + k]
-                                               : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rv[k]), jj));
+                        const bool two = soft != 0;
+                        const int jb = two ? __builtin_ctzll(soft) : ja;
+                        if (two) soft &= soft - 1;
+                        const float ra = LOWREG ? ls[(jbase + ja) * LS + k]
+                                                : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rv[k]), ja));
+                        const float rb = LOWREG ? ls[(jbase + jb) * LS + k]
+                                                : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rv[k]), jb));
+                        float xa[GS], xb[GS];
+                        read_genes<GS>(xa, xl + ja * XS);
+                        read_genes<GS>(xb, xl + jb * XS);
+                        keep<GS>(xb);  // both reads are issued before the branch below
 #pragma unroll
                         for (int sl = 0; sl < GS; ++sl) {
-                            const int g = lane + 64 * sl;
-                            const float xv = LOWREG ? xs[(jbase + jj) * XS + gl[sl]]
-                                                    : ((g < G) ? xs[(jbase + jj) * XS + g] : 0.f);
-                            const float d = xv - mfv[sl];
-                            const float wv = r * d;
-                            t1[k][sl] += wv;
-                            t2[k][sl] = fmaf(wv, d, t2[k][sl]);
+                            const float d = xa[sl] - mfv[sl];
+                            const float wv = ra * d;
+                            u1[sl] += wv;
+                            u2[sl] = fmaf(wv, d, u2[sl]);
                         }
+                        if (two) {
+#pragma unroll
+                            for (int sl = 0; sl < GS; ++sl) {
+                                const float d = xb[sl] - mfv[sl];
+                                const float wv = rb * d;
+                                u1[sl] += wv;
+                                u2[sl] = fmaf(wv, d, u2[sl]);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int sl = 0; sl < GS; ++sl) {
+                        t1[k][sl] = kSlabSums ? t1[k][sl] + u1[sl] : u1[sl];
+                        t2[k][sl] = kSlabSums ? t2[k][sl] + u2[sl] : u2[sl];
                     }
                 }
             }
@@ -493,12 +567,11 @@ __global__ __launch_bounds__(kBlock, 2) void k_estep_tiled(Shape s, Bufs bf)
             const double c0 = wave_sum((double)t0[k]);
             if (k < K) {
                 if (lane == 0) wd[w * KT + k] = c0;
+                if (gown) {
 #pragma unroll
-                for (int sl = 0; sl < GS; ++sl) {
-                    const int g = lane + 64 * sl;
-                    if (g < G) {
-                        ws[w * 2 * KG + k * G + g] = t1[k][sl];
-                        ws[w * 2 * KG + KG + k * G + g] = t2[k][sl];
+                    for (int sl = 0; sl < GS; ++sl) {
+                        ws[w * 2 * KG + k * G + g0 + sl] = t1[k][sl];
+                        ws[w * 2 * KG + KG + k * G + g0 + sl] = t2[k][sl];
                     }
                 }
             }
