@@ -356,6 +356,8 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
             float *lr = ls + j * LS;
             const float *xr = xs + j * XS;
             uint32_t done = 0;
+            int kone = 0;      // the best-bounded subpopulation and its exact l
+            float lone = 0.f;
             if (GB == G) {
                 if (act && half == 0) {
 #pragma unroll
@@ -380,6 +382,8 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
                 const float sh = act ? tail_sum<HG, !LOWREG>(xr, pt + kh * PS, GB + half * HG) : 0.f;
                 const float so = __shfl_xor(sh, 32, 64);
                 const float lkh = ccs[kh] - (pkh + (half == 0 ? sh + so : so + sh));
+                kone = kh;
+                lone = lkh;
                 uint32_t cm = 0;
 #pragma unroll
                 for (int k = 0; k < KT; ++k)
@@ -406,8 +410,43 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
             if (!act) done = 0;
             __builtin_amdgcn_wave_barrier();
 
-            // log-sum-exp over the computed set (lanes jl < 32 own the rows)
-            if (act && half == 0) {
+            // log-sum-exp over the computed set (lanes jl < 32 own the rows).  When every row
+            // of the slab has a single candidate (the usual case for well-separated
+            // subpopulations) the same arithmetic runs for that one term only: the results are
+            // those of the general form with the other terms absent.  (Not for KT = 16, where
+            // the second form costs more registers than it saves.)
+            bool single = false;
+            if constexpr (GB < G && KT <= 8) single = !__ballot(act && half == 0 && done != (1u << kone));
+            if (single) {
+                if (act && half == 0) {
+                    const float mx = lone;
+                    const float se = __expf(lone - mx);
+                    const float L = mx + __logf(se);
+                    float h = isfinite(L) ? 0.f : __int_as_float(0x7fc00000);
+                    float r = 0.f;
+                    const float dl = lone - L;
+                    if (dl > -kLogRCut) {
+                        r = __expf(dl);
+                        h -= r * dl;
+                    }
+#pragma unroll
+                    for (int k = 0; k < KT; ++k) {
+                        rv[k] = k == kone ? r : 0.f;
+                        t0[k] += rv[k];
+                    }
+                    if (r != 0.f) {
+                        mk |= 1u << kone;
+                        if (r == 1.f) mk |= kOneHot;
+                    }
+                    hacc += (double)h;
+                    if (LOWREG) {
+                        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                        for (int k = 0; k < KT; ++k)
+                            if (k < K) lr[k] = rv[k];
+                    }
+                }
+            } else if (act && half == 0) {
                 float l[KT];
 #pragma unroll
                 for (int k = 0; k < KT; ++k) l[k] = (done & (1u << k)) ? lr[k] : -INFINITY;
