@@ -66,25 +66,40 @@ struct Cfg {
     static_assert(2 * (4 * KT + 4) <= kT * LS, "per-wave counts must fit the l area");
 };
 
-// One wave's 32-row slab of a tile: G/8 16-byte loads per lane, coalesced along the rows.
-// Rows past the end of a ragged slab re-read its last row: the loads stay unconditional, so
-// the compiler keeps all of them in flight at once.
+// One wave's 32-row slab of a tile.  Its nr rows are contiguous in memory (nr G floats from
+// xrow); lane l reads the 16-byte pieces l, l + 64, ... of it.  Pieces past the end of a
+// ragged slab re-read its last piece: the loads stay unconditional, so the compiler keeps all
+// of them in flight at once, and the offsets are 32-bit from a uniform base.
 template <int G, bool OPAQUE>
-__device__ __forceinline__ void load_slab(f4 (&pre)[G / 8], const float *__restrict__ x, int64_t row0, int nr,
-                                          int lane)
+__device__ __forceinline__ void load_slab(f4 (&pre)[G / 8], const float *__restrict__ xrow, int nr, int lane)
 {
     constexpr int C4 = G / 4;
     // OPAQUE: an opaque copy of the lane index, so that the offsets below are recomputed at
     // every call instead of being hoisted out of the tile loop and held for its duration
     int ln = lane;
     if (OPAQUE) asm volatile("" : "+v"(ln));
+    const unsigned last = (unsigned)(nr * C4 - 1);
+#pragma unroll
+    for (int j = 0; j < G / 8; ++j) {
+        const unsigned i = min((unsigned)(ln + j * 64), last);
+        pre[j] = *(const f4 *)(xrow + 4 * i);
+    }
+}
+
+// Piece i of the slab belongs to row i / C4 of the wave's LDS slab (row stride G + 4): at
+// float offset 4 i + 4 row.  Every piece is stored; rows past a ragged end hold copies of the
+// last piece and are never read as data.
+template <int G, bool OPAQUE>
+__device__ __forceinline__ void store_slab(const f4 (&pre)[G / 8], float *xs, int lane)
+{
+    constexpr int C4 = G / 4;
+    int ln = lane;
+    if (OPAQUE) asm volatile("" : "+v"(ln));
 #pragma unroll
     for (int j = 0; j < G / 8; ++j) {
         const int i = ln + j * 64;
         const int row = i / C4;
-        const int col = (i - row * C4) * 4;
-        const int rr = row < nr ? row : nr - 1;
-        pre[j] = *(const f4 *)(x + (row0 + rr) * G + col);
+        *(f4 *)(xs + 4 * (i + row)) = pre[j];
     }
 }
 
@@ -108,21 +123,6 @@ __device__ __forceinline__ void keep(float (&v)[GS])
 {
 #pragma unroll
     for (int i = 0; i < GS; ++i) asm volatile("" ::"v"(v[i]));
-}
-
-template <int G, bool OPAQUE>
-__device__ __forceinline__ void store_slab(const f4 (&pre)[G / 8], float *xs, int nr, int lane)
-{
-    constexpr int C4 = G / 4, XS = G + 4;
-    int ln = lane;
-    if (OPAQUE) asm volatile("" : "+v"(ln));
-#pragma unroll
-    for (int j = 0; j < G / 8; ++j) {
-        const int i = ln + j * 64;
-        const int row = i / C4;
-        const int col = (i - row * C4) * 4;
-        if (row < nr) *(f4 *)(xs + row * XS + col) = pre[j];
-    }
 }
 
 // sum over N genes from g0 of (h x + q)^2, x from an LDS row, (h, q) from an LDS table row;
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
         f4 pre[C::LOADS];
         {
             const int nj0 = min(32, min(kT, nrc) - jbase);
-            if (nj0 > 0) load_slab<G, LOWREG>(pre, x, r0 + jbase, nj0, lane);
+            if (nj0 > 0) load_slab<G, LOWREG>(pre, x + (r0 + jbase) * G, nj0, lane);
         }
         const size_t kb = (size_t)bi * s.Kmax;
         const float *__restrict__ cc = bf.cc + kb;
@@ -283,10 +283,10 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
             const int nj = max(0, min(32, nr - jbase));
             // each wave stages, screens, sums and accumulates its own 32 rows: no workgroup
             // barrier inside the tile loop
-            if (nj > 0) store_slab<G, LOWREG>(pre, xs + jbase * XS, nj, lane);
+            if (nj > 0) store_slab<G, LOWREG>(pre, xs + jbase * XS, lane);
             if (t + 1 < ntiles) {
                 const int nj1 = min(32, min(kT, nrc - (t + 1) * kT) - jbase);
-                if (nj1 > 0) load_slab<G, LOWREG>(pre, x, r0 + (int64_t)(t + 1) * kT + jbase, nj1, lane);
+                if (nj1 > 0) load_slab<G, LOWREG>(pre, x + (r0 + (int64_t)(t + 1) * kT + jbase) * G, nj1, lane);
             }
             wave_lds_sync();
             if (nj == 0) continue;
