@@ -117,6 +117,13 @@ __device__ __forceinline__ void read_genes(float (&v)[GS], const float *p)
     }
 }
 
+// m with bit j cleared (one scalar instruction)
+__device__ __forceinline__ uint64_t clear_bit(uint64_t m, int j)
+{
+    asm("s_bitset0_b64 %0, %1" : "+s"(m) : "s"(j));
+    return m;
+}
+
 // the values are needed here: a read of them is not moved into a later conditional block
 template <int GS>
 __device__ __forceinline__ void keep(float (&v)[GS])
@@ -318,36 +325,33 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
                 }
             } else {
             // A. screen: partial sums over the first GB genes; lane (row j, half) takes
-            //    subpopulations half, half + 2, ...
+            //    subpopulations half, half + 2, ...  Every lane writes all of its slots (a
+            //    skipped subpopulation k >= K, or a row past the end, leaves a value that is
+            //    never read), so that only the test k < K branches.
             {
-                float acc[KH];
-#pragma unroll
-                for (int i = 0; i < KH; ++i) acc[i] = 0.f;
                 const float *xa = xs + j * XS;
+                f4 va[GB / 4];
 #pragma unroll
-                for (int gb = 0; gb < GB; gb += 4) {
-                    const f4 va = *(const f4 *)(xa + gb);
+                for (int gb = 0; gb < GB; gb += 4) va[gb / 4] = *(const f4 *)(xa + gb);
 #pragma unroll
-                    for (int i = 0; i < KH; ++i) {
-                        const int k = half + 2 * i;
-                        if (k < K) {
+                for (int i = 0; i < KH; ++i) {
+                    const int k = half + 2 * i;
+                    float acc = 0.f;
+                    if (k < K) {
+#pragma unroll
+                        for (int gb = 0; gb < GB; gb += 4) {
                             const float *p = pt + k * PS + 2 * gb;
                             const float h0 = p[0], q0 = p[1], h1 = p[2], q1 = p[3];
                             const float h2 = p[4], q2 = p[5], h3 = p[6], q3 = p[7];
+                            const f4 v = va[gb / 4];
                             float u;
-                            u = fmaf(va.x, h0, q0); acc[i] = fmaf(u, u, acc[i]);
-                            u = fmaf(va.y, h1, q1); acc[i] = fmaf(u, u, acc[i]);
-                            u = fmaf(va.z, h2, q2); acc[i] = fmaf(u, u, acc[i]);
-                            u = fmaf(va.w, h3, q3); acc[i] = fmaf(u, u, acc[i]);
+                            u = fmaf(v.x, h0, q0); acc = fmaf(u, u, acc);
+                            u = fmaf(v.y, h1, q1); acc = fmaf(u, u, acc);
+                            u = fmaf(v.z, h2, q2); acc = fmaf(u, u, acc);
+                            u = fmaf(v.w, h3, q3); acc = fmaf(u, u, acc);
                         }
                     }
-                }
-                if (act) {
-#pragma unroll
-                    for (int i = 0; i < KH; ++i) {
-                        const int k = half + 2 * i;
-                        if (k < K) ls[j * LS + k] = acc[i];
-                    }
+                    ls[j * LS + k] = acc;
                 }
             }
             wave_lds_sync();
@@ -503,7 +507,6 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
             //    and that sum is added to the wave's running sum; otherwise the rows are
             //    added to the running sum directly.
             if (nj > 0) {
-                const bool own = act && half == 0;
                 // the lane's first gene, as an opaque value in the register-light schedule: the
                 // LDS addresses below are formed from it here rather than hoisted out of the
                 // tile loop and held
@@ -511,13 +514,15 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
                 if (LOWREG) asm volatile("" : "+v"(gq));
                 const float *xl = xs + jbase * XS + gq;
                 constexpr bool kSlabSums = KT > 8;
+                // mk is zero outside the rows this wave owns
+                const uint64_t hard = __ballot(mk & kOneHot);
 #pragma unroll
                 for (int k = 0; k < KT; ++k) {
                     if (k >= K) break;
-                    const bool nzk = own && (mk & (1u << k));
-                    uint64_t one = __ballot(nzk && (mk & kOneHot));
-                    uint64_t soft = __ballot(nzk && !(mk & kOneHot));
-                    if (!(one | soft)) continue;
+                    const uint64_t rows = __ballot((mk >> k) & 1u);
+                    if (!rows) continue;
+                    uint64_t one = rows & hard;
+                    uint64_t soft = rows & ~hard;
                     float mfv[GS], u1[GS], u2[GS];
 #pragma unroll
                     for (int sl = 0; sl < GS; ++sl) {
@@ -532,10 +537,10 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
                     }
                     while (one) {
                         const int ja = __builtin_ctzll(one);
-                        one &= one - 1;
+                        one = clear_bit(one, ja);
                         const bool two = one != 0;
                         const int jb = two ? __builtin_ctzll(one) : ja;
-                        if (two) one &= one - 1;
+                        one = clear_bit(one, jb);  // no-op when it was the last row
                         float xa[GS], xb[GS];
                         read_genes<GS>(xa, xl + ja * XS);
                         read_genes<GS>(xb, xl + jb * XS);
@@ -557,10 +562,10 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
                     }
                     while (soft) {
                         const int ja = __builtin_ctzll(soft);
-                        soft &= soft - 1;
+                        soft = clear_bit(soft, ja);
                         const bool two = soft != 0;
                         const int jb = two ? __builtin_ctzll(soft) : ja;
-                        if (two) soft &= soft - 1;
+                        soft = clear_bit(soft, jb);  // no-op when it was the last row
                         const float ra = LOWREG ? ls[(jbase + ja) * LS + k]
                                                 : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rv[k]), ja));
                         const float rb = LOWREG ? ls[(jbase + jb) * LS + k]
