@@ -373,9 +373,18 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
                 float U[KT];
                 float best = -INFINITY;
                 int kh = 0;
+                // the row's partial sums and the c_k, read whole (16-byte reads, no branches)
+                float lv[KT], cv[KT];
+#pragma unroll
+                for (int q = 0; q < KT; q += 4) {
+                    const f4 a = *(const f4 *)(lr + q);
+                    const f4 c = *(const f4 *)(ccs + q);
+                    lv[q] = a.x, lv[q + 1] = a.y, lv[q + 2] = a.z, lv[q + 3] = a.w;
+                    cv[q] = c.x, cv[q + 1] = c.y, cv[q + 2] = c.z, cv[q + 3] = c.w;
+                }
 #pragma unroll
                 for (int k = 0; k < KT; ++k) {
-                    U[k] = (k < K && act) ? ccs[k] - lr[k] : -INFINITY;
+                    U[k] = (k < K && act) ? cv[k] - lv[k] : -INFINITY;
                     if (U[k] > best) {
                         best = U[k];
                         kh = k;
@@ -416,38 +425,26 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
 
             // log-sum-exp over the computed set (lanes jl < 32 own the rows).  When every row
             // of the slab has a single candidate (the usual case for well-separated
-            // subpopulations) the same arithmetic runs for that one term only: the results are
-            // those of the general form with the other terms absent.  (Not for KT = 16, where
-            // the second form costs more registers than it saves.)
+            // subpopulations) the exact values are written directly: responsibility 1 and entropy
+            // term 0 for a finite l (r = 0 and a NaN entropy otherwise, as in the general form).
+            // (Not for KT = 16, where the second form costs more registers than it saves.)
             bool single = false;
             if constexpr (GB < G && KT <= 8) single = !__ballot(act && half == 0 && done != (1u << kone));
             if (single) {
                 if (act && half == 0) {
-                    const float mx = lone;
-                    const float se = __expf(lone - mx);
-                    const float L = mx + __logf(se);
-                    float h = isfinite(L) ? 0.f : __int_as_float(0x7fc00000);
-                    float r = 0.f;
-                    const float dl = lone - L;
-                    if (dl > -kLogRCut) {
-                        r = __expf(dl);
-                        h -= r * dl;
-                    }
+                    const bool fin = isfinite(lone);
+                    const float r = fin ? 1.f : 0.f;
 #pragma unroll
                     for (int k = 0; k < KT; ++k) {
                         rv[k] = k == kone ? r : 0.f;
                         t0[k] += rv[k];
                     }
-                    if (r != 0.f) {
-                        mk |= 1u << kone;
-                        if (r == 1.f) mk |= kOneHot;
-                    }
-                    hacc += (double)h;
+                    if (fin) mk |= (1u << kone) | kOneHot;
+                    hacc += fin ? 0.0 : (double)__int_as_float(0x7fc00000);
                     if (LOWREG) {
                         __builtin_amdgcn_wave_barrier();
 #pragma unroll
-                        for (int k = 0; k < KT; ++k)
-                            if (k < K) lr[k] = rv[k];
+                        for (int q = 0; q < KT; q += 4) *(f4 *)(lr + q) = f4{rv[q], rv[q + 1], rv[q + 2], rv[q + 3]};
                     }
                 }
             } else if (act && half == 0) {
@@ -490,8 +487,7 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
                     // the responsibilities replace the row's l values in LDS for the statistics
                     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-                    for (int k = 0; k < KT; ++k)
-                        if (k < K) lr[k] = rv[k];
+                    for (int q = 0; q < KT; q += 4) *(f4 *)(lr + q) = f4{rv[q], rv[q + 1], rv[q + 2], rv[q + 3]};
                 }
             }
             if (LOWREG) wave_lds_sync();
