@@ -448,32 +448,37 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
                     }
                 }
             } else if (act && half == 0) {
+                // every term is formed and the computed set selects it (no branches); adding
+                // +0 for a term outside the set leaves a sum unchanged
                 float l[KT];
 #pragma unroll
-                for (int k = 0; k < KT; ++k) l[k] = (done & (1u << k)) ? lr[k] : -INFINITY;
+                for (int q = 0; q < KT; q += 4) {
+                    const f4 a = *(const f4 *)(lr + q);
+                    l[q] = a.x, l[q + 1] = a.y, l[q + 2] = a.z, l[q + 3] = a.w;
+                }
+#pragma unroll
+                for (int k = 0; k < KT; ++k) l[k] = (done & (1u << k)) ? l[k] : -INFINITY;
                 float mx = l[0];
 #pragma unroll
                 for (int k = 1; k < KT; ++k) mx = fmaxf(mx, l[k]);
                 float se = 0.f;
 #pragma unroll
-                for (int k = 0; k < KT; ++k)
-                    if (done & (1u << k)) se += __expf(l[k] - mx);
+                for (int k = 0; k < KT; ++k) {
+                    const float e = __expf(l[k] - mx);
+                    se += (done & (1u << k)) ? e : 0.f;
+                }
                 const float L = mx + __logf(se);
                 float h = isfinite(L) ? 0.f : __int_as_float(0x7fc00000);
                 int nz = 0;
 #pragma unroll
                 for (int k = 0; k < KT; ++k) {
-                    if (done & (1u << k)) {
-                        const float dl = l[k] - L;
-                        if (dl > -kLogRCut) {
-                            rv[k] = __expf(dl);
-                            h -= rv[k] * dl;
-                        }
-                    }
-                    if (rv[k] != 0.f) {
-                        mk |= 1u << k;
-                        ++nz;
-                    }
+                    const float dl = l[k] - L;
+                    const bool take = (done & (1u << k)) && dl > -kLogRCut;
+                    const float e = __expf(dl);
+                    rv[k] = take ? e : 0.f;
+                    h = take ? h - rv[k] * dl : h;
+                    mk |= rv[k] != 0.f ? 1u << k : 0u;
+                    nz += rv[k] != 0.f;
                     t0[k] += rv[k];
                 }
                 if (nz == 1) {
