@@ -124,14 +124,6 @@ __device__ __forceinline__ uint64_t clear_bit(uint64_t m, int j)
     return m;
 }
 
-// the values are needed here: a read of them is not moved into a later conditional block
-template <int GS>
-__device__ __forceinline__ void keep(float (&v)[GS])
-{
-#pragma unroll
-    for (int i = 0; i < GS; ++i) asm volatile("" ::"v"(v[i]));
-}
-
 // sum over N genes from g0 of (h x + q)^2, x from an LDS row, (h, q) from an LDS table row;
 // UNROLL: all loads issued up front (more registers) or one block of 4 genes at a time
 template <int N, bool UNROLL>
@@ -501,8 +493,9 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
 
             // C. statistics over the same rows, lanes over genes.  For each subpopulation
             //    walk the rows whose responsibility for it is nonzero, two rows per step so
-            //    that their LDS reads overlap; rows with a single responsibility of exactly 1
-            //    skip the multiplication.  Rows are added in increasing order (one-hot rows
+            //    that their LDS reads overlap (a step without a second row adds the first
+            //    again with weight 0, which leaves the sums unchanged for finite data); rows
+            //    with a single responsibility of exactly 1 skip the multiplication.  Rows are added in increasing order (one-hot rows
             //    first).  With KT = 16 the subpopulation loop is not unrolled, so the sums
             //    cannot be indexed statically: the slab's rows are summed in two registers
             //    and that sum is added to the wave's running sum; otherwise the rows are
@@ -542,23 +535,22 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
                         const bool two = one != 0;
                         const int jb = two ? __builtin_ctzll(one) : ja;
                         one = clear_bit(one, jb);  // no-op when it was the last row
+                        // without a second row, row ja enters again with weight 0
+                        const float w = two ? 1.f : 0.f;
                         float xa[GS], xb[GS];
                         read_genes<GS>(xa, xl + ja * XS);
                         read_genes<GS>(xb, xl + jb * XS);
-                        keep<GS>(xb);  // both reads are issued before the branch below
 #pragma unroll
                         for (int sl = 0; sl < GS; ++sl) {
                             const float d = xa[sl] - mfv[sl];
                             u1[sl] += d;
                             u2[sl] = fmaf(d, d, u2[sl]);
                         }
-                        if (two) {
 #pragma unroll
-                            for (int sl = 0; sl < GS; ++sl) {
-                                const float d = xb[sl] - mfv[sl];
-                                u1[sl] += d;
-                                u2[sl] = fmaf(d, d, u2[sl]);
-                            }
+                        for (int sl = 0; sl < GS; ++sl) {
+                            const float d = xb[sl] - mfv[sl];
+                            u1[sl] = fmaf(d, w, u1[sl]);
+                            u2[sl] = fmaf(d * w, d, u2[sl]);
                         }
                     }
                     while (soft) {
@@ -569,12 +561,12 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
                         soft = clear_bit(soft, jb);  // no-op when it was the last row
                         const float ra = LOWREG ? ls[(jbase + ja) * LS + k]
                                                 : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rv[k]), ja));
-                        const float rb = LOWREG ? ls[(jbase + jb) * LS + k]
-                                                : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rv[k]), jb));
+                        const float rb0 = LOWREG ? ls[(jbase + jb) * LS + k]
+                                                 : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rv[k]), jb));
+                        const float rb = two ? rb0 : 0.f;
                         float xa[GS], xb[GS];
                         read_genes<GS>(xa, xl + ja * XS);
                         read_genes<GS>(xb, xl + jb * XS);
-                        keep<GS>(xb);  // both reads are issued before the branch below
 #pragma unroll
                         for (int sl = 0; sl < GS; ++sl) {
                             const float d = xa[sl] - mfv[sl];
@@ -582,14 +574,12 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
                             u1[sl] += wv;
                             u2[sl] = fmaf(wv, d, u2[sl]);
                         }
-                        if (two) {
 #pragma unroll
-                            for (int sl = 0; sl < GS; ++sl) {
-                                const float d = xb[sl] - mfv[sl];
-                                const float wv = rb * d;
-                                u1[sl] += wv;
-                                u2[sl] = fmaf(wv, d, u2[sl]);
-                            }
+                        for (int sl = 0; sl < GS; ++sl) {
+                            const float d = xb[sl] - mfv[sl];
+                            const float wv = rb * d;
+                            u1[sl] += wv;
+                            u2[sl] = fmaf(wv, d, u2[sl]);
                         }
                     }
 #pragma unroll
