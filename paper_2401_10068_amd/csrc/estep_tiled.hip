@@ -10,8 +10,8 @@
 // workgroup barrier inside the tile loop): it stages them in its slab of the
 // LDS tile (row stride G+4 floats) while the next slab is prefetched into
 // registers.  Per slab:
-//   A. Screen.  Lane (row j, half) forms, over the first GB = min(G, 16)
-//      genes, the partial sums P_nk of subpopulations half, half+2, ...  Every
+//   A. Screen.  Lane (row j, half) forms, over the first GB genes (16, or 8
+//      when K is above 8), the partial sums P_nk of subpopulations half, half+2, ...  Every
 //      term is non-negative, so U_nk = c_k - P_nk bounds l_nk from above (also
 //      in FP32: adding non-negative terms never lowers a rounded sum).
 //      Coefficients are LDS broadcasts from the chunk's (h, q) table.
@@ -53,7 +53,9 @@ struct Cfg {
     static constexpr int KH = KT / 2;                    // subpopulations per lane (screen)
     static constexpr int GS = (G + 63) / 64;             // genes per lane (statistics): GS l .. GS l + GS - 1
     static constexpr int LOADS = G / 8;                  // 16-byte loads per lane per 32-row slab
-    static constexpr int GB = G < 16 ? G : 16;           // screened genes
+    // screened genes: 16, or 8 for KT = 16 (K above 8), where screening every subpopulation
+    // over 16 genes costs more than the exact terms of the extra candidates that 8 let through
+    static constexpr int GB = KT > 8 ? 8 : (G < 16 ? G : 16);
     static constexpr int HG = (G - GB) / 2;              // remaining genes per half row
     static constexpr int LDS_BYTES = (kT * XS + kT * LS + KT * PS + KT + KT * G) * 4;
     // waves per SIMD that the LDS allows (160 KB per CU, four waves per workgroup, one per
