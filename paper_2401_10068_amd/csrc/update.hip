@@ -28,7 +28,7 @@ struct MShared {
     double red[kMBlock / 64];
     double ak[kMaxK], psi_ak[kMaxK], lg_ak[kMaxK], term_k[kMaxK];
     double tmp[kMaxKG];
-    double asum, psum;
+    double asum, psum, lg_asum, lg_prior;
     int bad;
 };
 
@@ -233,15 +233,19 @@ __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, in
     }
     if (bad) atomicOr(&sh.bad, 1);
     __syncthreads();
-    if (tid < 64) {
+    // digamma and lgamma of sum(alpha) and the Dirichlet prior's normaliser, in different
+    // waves at the same time
+    if (tid < 64 || (!init_mode && tid < 128)) {
         double x = 0.0;
-        for (int k = tid; k < K; k += 64) x += sh.ak[k];
+        for (int k = tid & 63; k < K; k += 64) x += sh.ak[k];
         x = wave_sum(x);
         if (tid == 0) {
             sh.asum = x;
             sh.psum = dev_digamma(x);
         }
+        if (tid == 64) sh.lg_asum = dev_lgamma(x);
     }
+    if (!init_mode && tid == 128) sh.lg_prior = dev_lgamma(K * p.alpha0) - K * dev_lgamma(p.alpha0);
     __syncthreads();
     coef_rows(v, sh, &p, !init_mode);
     {
@@ -265,7 +269,7 @@ __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, in
             }
         } else {
             double L = sh.red[0] + H;
-            L += dev_lgamma(K * p.alpha0) - K * dev_lgamma(p.alpha0) - dev_lgamma(sh.asum);
+            L += sh.lg_prior - sh.lg_asum;
             for (int k = 0; k < K; ++k) L += sh.term_k[k];
             if (!isfinite(L)) sh.bad = 1;
             if (sh.bad) {
