@@ -242,6 +242,57 @@ def workload(name: str):
     raise KeyError(name)
 
 
+# ----------------------------------------------------------------------------- linear mixing
+STREAM_LM_PROFILE, STREAM_LM_BETA, STREAM_LM_NOISE = 4, 5, 6
+
+# The paper's synthetic study (Section 4): N = 3 networks, rho = 100 and this precision matrix.
+LM_LAMBDA = np.linalg.inv(np.array([[0.01, 0.005], [0.005, 0.008]]))
+
+
+def linmix_dataset(seed: int, V: int, K_true, rho: float = 100.0, Lam=None, block: int = 1 << 20):
+    """Synthetic genes for the paper's linear-mixing model (Section 3.3, eqs 2-4; Section 4).
+
+    The expression profiles d_i (N values in {0, 1}) stand in for the Boolean-network outputs
+    the paper used (not available): each entry is 1 when the top bit of a Philox word is set
+    (stream 4, index = gene, sub = entry).  beta_i = K + L z_i with L L^T = Lambda^-1 and z_i
+    standard normal (Box-Muller, stream 5, sub = pair of components); the reading is
+    r_i = D_i^T beta_i + mu_i + e_i / sqrt(rho), e_i standard normal (stream 6), with
+    mu_i = d_{i,N} and D_i = d_{i,1..N-1} - d_{i,N}.  Returns (r[V], d[V, N]) in FP64.
+    """
+    K_true = np.asarray(K_true, dtype=np.float64)
+    M = K_true.size
+    N = M + 1
+    if Lam is None:
+        Lam = LM_LAMBDA if M == 2 else np.eye(M) / 0.01
+    L = np.linalg.cholesky(np.linalg.inv(np.asarray(Lam, dtype=np.float64)))
+    k0, k1 = int(seed) & _MASK, 0x4C4D5642  # key (seed, "LMVB")
+    r = np.empty(V)
+    d = np.empty((V, N))
+    for lo in range(0, V, block):
+        hi = min(V, lo + block)
+        g = np.arange(lo, hi, dtype=np.uint64)
+        glo, ghi = g & np.uint64(_MASK), g >> np.uint64(32)
+        j = np.arange(N, dtype=np.uint64)
+        w = philox4x32_10(glo[:, None], ghi[:, None], j[None, :], STREAM_LM_PROFILE, k0, k1)
+        dd = (w[0] >> np.uint64(31)).astype(np.float64)
+        npair = (M + 1) // 2
+        jp = np.arange(npair, dtype=np.uint64)
+        w = philox4x32_10(glo[:, None], ghi[:, None], jp[None, :], STREAM_LM_BETA, k0, k1)
+        rad = np.sqrt(-2.0 * np.log(u53(w[0], w[1])))
+        th = 2.0 * np.pi * u53(w[2], w[3])
+        z = np.empty((hi - lo, 2 * npair))
+        z[:, 0::2] = rad * np.cos(th)
+        z[:, 1::2] = rad * np.sin(th)
+        beta = K_true[None, :] + z[:, :M] @ L.T
+        w = philox4x32_10(glo, ghi, 0, STREAM_LM_NOISE, k0, k1)
+        eps = np.sqrt(-2.0 * np.log(u53(w[0], w[1]))) * np.cos(2.0 * np.pi * u53(w[2], w[3]))
+        mu = dd[:, -1]
+        D = dd[:, :-1] - dd[:, -1:]
+        r[lo:hi] = np.einsum("vi,vi->v", D, beta) + mu + eps / math.sqrt(rho)
+        d[lo:hi] = dd
+    return r, d
+
+
 # ----------------------------------------------------------------------------- device twin
 _glib = None
 
