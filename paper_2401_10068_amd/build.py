@@ -1,6 +1,6 @@
 """Build the gfx950 shared libraries in-tree with hipcc.
 
-``libcavi.so``        the CAVI library (include/cavi.h)
+``libcavi.so``        the CAVI library (include/cavi.h) and the linear-mixing VB (include/lmvb.h)
 ``libcavi_synth.so``  the on-device input generator (synth.py's definition)
 """
 from __future__ import annotations
@@ -23,7 +23,7 @@ COMMON = [
 ]
 
 LIBS = {
-    "libcavi.so": ["cavi_kernels.hip", "estep_tiled.hip", "update.hip", "warmstart.hip", "cavi_api.cpp",
+    "libcavi.so": ["cavi_kernels.hip", "estep_tiled.hip", "update.hip", "warmstart.hip", "lmvb.hip", "cavi_api.cpp",
                    "warmstart_api.cpp"],
     "libcavi_synth.so": ["synth.hip"],
 }

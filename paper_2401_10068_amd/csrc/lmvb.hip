@@ -1,0 +1,824 @@
+// gfx950 kernels and C ABI (include/lmvb.h) of the variational Bayes for the paper's own
+// linear-mixing model (Section 3.3, eqs 2-8), with the updates of eqs 16-31 in the order of the
+// steps of Section 3.5.
+//
+// One sweep is three launches:
+//   k_lm_pass<M>     one thread per gene: q(beta_i) from the current coefficients (eqs 20, 21),
+//                    its moments (eqs 26, 27), and the gene's terms of the sums that the global
+//                    updates need (sum m_i, sum E[beta_i beta_i^T], the bracket of eq 17 and
+//                    ln|P_i|); FP64 sums per 8192-gene chunk in a fixed order;
+//   k_lm_reduce      the chunk sums in 16 contiguous groups, each in chunk order;
+//   k_lm_global<M>   the groups in order, then q(K, Lambda) (eqs 24, 25), the lower bound, the
+//                    convergence test, and q(rho) (eqs 16, 17) with the coefficients E[rho],
+//                    E[Lambda], E[Lambda K] (eqs 28, 29, 31) of the next pass.
+// The gene factors are not stored: they are a function of the data and of the coefficients of the
+// pass that formed them, which the state keeps (lmvb_get_genes recomputes them).
+// Everything is FP64, as in the paper.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/lmvb.h"
+#include "cavi_impl.h"
+#include "devmath.h"
+
+namespace {
+
+constexpr int kMaxM = 7;
+constexpr int kThreads = 256;
+constexpr int kPerThread = 32;
+constexpr int kChunk = kThreads * kPerThread;              // genes per chunk
+constexpr int kMaxS = kMaxM + kMaxM * (kMaxM + 1) / 2 + 2;  // sums per chunk
+constexpr int kGroups = 16;                                 // first-level reduction groups
+constexpr int kRedThreads = 1024;
+constexpr int kHistCap = 1 << 16;
+constexpr double kLn2Pi = 1.8378770664093454835606594728112;
+constexpr double kLnPi = 1.1447298858494001741434273513531;
+constexpr double kLn2 = 0.69314718055994530941723212145818;
+
+// Coefficients of one pass over the genes (the current q(rho) and q(K, Lambda) through their
+// expectations), together with the q(rho) they came from.
+struct Coef {
+    double a_rho, b_rho, Erho;
+    double ELam[kMaxM * kMaxM];
+    double ELamK[kMaxM];
+};
+
+struct Prior {
+    double a0, b0, q0, n0;
+    double K0[kMaxM];
+    double L0[kMaxM * kMaxM];
+    double L0inv[kMaxM * kMaxM];
+    double lnB0;       // ln of the Wishart prior's normaliser (0 when the prior is improper)
+    double lg_a0;      // lgamma(a0)
+};
+
+struct State {
+    double a_rho, b_rho;   // q(rho)
+    double K0K[kMaxM];     // q(K | Lambda) mean
+    double W[kMaxM * kMaxM];  // q(Lambda) scale matrix
+    double nu, kappa;
+    double elbo, tol;
+    int32_t sweeps, call_sweeps, max_call, stop_on_conv, converged, numeric, swept, pad;
+    Coef coef;  // next pass
+    Coef used;  // the pass that formed the current q(beta)
+};
+
+struct Shape {
+    int64_t V;
+    int32_t N, M, nchunk, S;
+};
+
+// position of E[beta beta^T]_{ik} (i <= k) in a chunk's sums: after the M means, row-major upper triangle
+__host__ __device__ constexpr int tri(int M, int i, int k) { return M + i * M - i * (i - 1) / 2 + (k - i); }
+
+__device__ __forceinline__ bool skipped(const State *s)
+{
+    return s->numeric || s->call_sweeps >= s->max_call || (s->stop_on_conv && s->converged);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// q(beta_i) of one gene: P = E[Lambda] + E[rho] D D^T (eq 20) factored as L L^T, the mean
+// m = P^-1 (E[Lambda K] + E[rho] D e) (eq 21, e = r - mu), S = P^-1 = L^-T L^-1 and det P.
+template <int M>
+__device__ __forceinline__ void gene_factor(const double (&D)[M], double e, const Coef &c, double (&m)[M],
+                                            double (&S)[M][M], double &detP)
+{
+    double L[M][M], Li[M][M], y[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) L[i][j] = c.ELam[i * M + j] + c.Erho * D[i] * D[j];
+    detP = 1.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        double s = L[j][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
+        detP *= s;
+        const double ljj = sqrt(s);
+        L[j][j] = ljj;
+        Li[j][j] = 1.0 / ljj;
+#pragma unroll
+        for (int i = j + 1; i < M; ++i) {
+            double t = L[i][j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+            L[i][j] = t * Li[j][j];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        double s = c.ELamK[i] + c.Erho * D[i] * e;
+#pragma unroll
+        for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
+        y[i] = s * Li[i][i];
+    }
+#pragma unroll
+    for (int i = M - 1; i >= 0; --i) {
+        double s = y[i];
+#pragma unroll
+        for (int k = i + 1; k < M; ++k) s -= L[k][i] * m[k];
+        m[i] = s * Li[i][i];
+    }
+    // L^-1, lower triangular, by columns
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+#pragma unroll
+        for (int i = j + 1; i < M; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = j; k < i; ++k) s -= L[i][k] * Li[k][j];
+            Li[i][j] = s * Li[i][i];
+        }
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+        for (int j = i; j < M; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = j; k < M; ++k) s += Li[k][i] * Li[k][j];
+            S[i][j] = s;
+            S[j][i] = s;
+        }
+}
+
+// One thread per gene.  Per chunk: [sum m (M) | sum E[beta beta^T] (upper triangle, row-major) |
+// sum of the eq 17 bracket | sum ln det P_i], each summed per thread over its genes in order,
+// then over the wave's lanes by a fixed butterfly, then over the four waves in order.
+// INIT: the gene factors of the initial state (m_i = 1/N, P_i = L0) instead of the coefficients.
+template <int M, bool INIT>
+__global__ __launch_bounds__(kThreads) void k_lm_pass(Shape sh, const double *__restrict__ r,
+                                                       const double *__restrict__ d, const State *st,
+                                                       const Prior *pr, double *__restrict__ partials)
+{
+    constexpr int N = M + 1, S = M + M * (M + 1) / 2 + 2;
+    if (!INIT && skipped(st)) return;
+    __shared__ double red[kThreads / 64][S];
+    const Coef c = st->coef;
+    double Sinit[M][M];
+    if (INIT) {
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int j = 0; j < M; ++j) Sinit[i][j] = pr->L0inv[i * M + j];
+    }
+    double acc[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] = 0.0;
+    const int64_t g0 = (int64_t)blockIdx.x * kChunk + threadIdx.x;
+    for (int j = 0; j < kPerThread; ++j) {
+        const int64_t g = g0 + (int64_t)j * kThreads;
+        if (g >= sh.V) break;
+        double dv[N];
+#pragma unroll
+        for (int q = 0; q < N; ++q) dv[q] = d[g * N + q];
+        const double e = r[g] - dv[N - 1];  // r_i - mu_i
+        double D[M], m[M], Sg[M][M];
+#pragma unroll
+        for (int q = 0; q < M; ++q) D[q] = dv[q] - dv[N - 1];
+        double detP = 1.0;
+        if (INIT) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                m[i] = 1.0 / N;
+#pragma unroll
+                for (int k = 0; k < M; ++k) Sg[i][k] = Sinit[i][k];
+            }
+        } else {
+            gene_factor<M>(D, e, c, m, Sg, detP);
+        }
+        // E[beta beta^T] = m m^T + S (eq 27) and the bracket of eq 17
+        double Dm = 0.0, quad = 0.0;
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            acc[i] += m[i];
+            Dm += D[i] * m[i];
+        }
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int k = i; k < M; ++k) {
+                const double ebb = m[i] * m[k] + Sg[i][k];
+                acc[tri(M, i, k)] += ebb;
+                quad += (i == k ? 1.0 : 2.0) * D[i] * ebb * D[k];
+            }
+        acc[S - 2] += e * e - 2.0 * e * Dm + quad;
+        acc[S - 1] += INIT ? 0.0 : log(detP);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const double w = wave_sum(acc[s]);
+        if (lane == 0) red[wv][s] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < S) {
+        double t = red[0][threadIdx.x];
+#pragma unroll
+        for (int w = 1; w < kThreads / 64; ++w) t += red[w][threadIdx.x];
+        partials[(size_t)blockIdx.x * S + threadIdx.x] = t;
+    }
+}
+
+// Group b sums chunks [b n / 16, (b + 1) n / 16): wave v a contiguous 1/16 of them in chunk order
+// (eight loads in flight), then the 16 waves in order.  Lane s holds sum s.
+__global__ __launch_bounds__(kRedThreads) void k_lm_reduce(Shape sh, const State *st, int init_mode,
+                                                          const double *__restrict__ partials,
+                                                          double *__restrict__ level1)
+{
+    if (!init_mode && skipped(st)) return;
+    __shared__ double part[kRedThreads / 64][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = kRedThreads / 64;
+    const int b = blockIdx.x;
+    const int c0 = (int)(((int64_t)sh.nchunk * b) / kGroups), c1 = (int)(((int64_t)sh.nchunk * (b + 1)) / kGroups);
+    const int w0 = c0 + (int)(((int64_t)(c1 - c0) * wv) / nw), w1 = c0 + (int)(((int64_t)(c1 - c0) * (wv + 1)) / nw);
+    const int s = min(lane, sh.S - 1);
+    double acc = 0.0;
+    for (int c = w0; c < w1; c += 8) {
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = partials[(size_t)min(c + j, w1 - 1) * sh.S + s];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (c + j < w1) acc += v[j];
+    }
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && lane < sh.S) {
+        double t = part[0][lane];
+        for (int w = 1; w < nw; ++w) t += part[w][lane];
+        level1[(size_t)b * kMaxS + lane] = t;
+    }
+}
+
+// Cholesky factor of an SPD M x M matrix (row-major), its inverse and ln det; false if not SPD.
+template <int M>
+__device__ bool spd_inverse(const double *A, double *Ainv, double &lndet)
+{
+    double L[M][M], Li[M][M];
+    lndet = 0.0;
+    for (int j = 0; j < M; ++j) {
+        double s = A[j * M + j];
+        for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
+        if (!(s > 0.0)) return false;
+        const double ljj = sqrt(s);
+        lndet += 2.0 * log(ljj);
+        L[j][j] = ljj;
+        Li[j][j] = 1.0 / ljj;
+        for (int i = j + 1; i < M; ++i) {
+            double t = A[i * M + j];
+            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+            L[i][j] = t * Li[j][j];
+        }
+    }
+    for (int j = 0; j < M; ++j)
+        for (int i = j + 1; i < M; ++i) {
+            double s = 0.0;
+            for (int k = j; k < i; ++k) s -= L[i][k] * Li[k][j];
+            Li[i][j] = s * Li[i][i];
+        }
+    for (int i = 0; i < M; ++i)
+        for (int j = i; j < M; ++j) {
+            double s = 0.0;
+            for (int k = j; k < M; ++k) s += Li[k][i] * Li[k][j];
+            Ainv[i * M + j] = s;
+            Ainv[j * M + i] = s;
+        }
+    return true;
+}
+
+// Coefficients of the next pass from q(rho) = Gamma(a, b) and q(K, Lambda) (eqs 28, 29, 31).
+template <int M>
+__device__ void next_coef(Coef &c, double a, double b, const double *W, const double *K0K, double nu)
+{
+    c.a_rho = a;
+    c.b_rho = b;
+    c.Erho = a / b;
+    for (int i = 0; i < M; ++i) {
+        double t = 0.0;
+        for (int j = 0; j < M; ++j) {
+            c.ELam[i * M + j] = nu * W[i * M + j];
+            t += W[i * M + j] * K0K[j];
+        }
+        c.ELamK[i] = nu * t;
+    }
+}
+
+// One workgroup of 64 threads.  Lanes j < M form digamma and lgamma of (nu + 1 - (j + 1)) / 2
+// (Wishart expectations), lanes M and M + 1 digamma and lgamma of a_rho; lane 0 does the rest.
+template <int M>
+__global__ __launch_bounds__(64) void k_lm_global(Shape sh, State *st, const Prior *pr, int init_mode,
+                                                  const double *__restrict__ level1, double *__restrict__ hist)
+{
+    if (!init_mode && skipped(st)) return;
+    constexpr int S = M + M * (M + 1) / 2 + 2;
+    __shared__ double tot[kMaxS];
+    __shared__ double sp[2][kMaxM + 2];
+    const int lane = threadIdx.x;
+    const double V = (double)sh.V;
+    const double nu = pr->n0 + V, kappa = pr->q0 + V;
+    const Coef used = st->coef;
+    if (lane < S) {
+        double t = level1[lane];
+        for (int b = 1; b < kGroups; ++b) t += level1[(size_t)b * kMaxS + lane];
+        tot[lane] = t;
+    }
+    if (!init_mode) {
+        if (lane < M) {
+            const double x = 0.5 * (nu - lane);  // (nu + 1 - j) / 2 for j = lane + 1
+            sp[0][lane] = cavi::dev_digamma(x);
+            sp[1][lane] = cavi::dev_lgamma(x);
+        } else if (lane == M) {
+            sp[0][M] = cavi::dev_digamma(used.a_rho);
+        } else if (lane == M + 1) {
+            sp[1][M] = cavi::dev_lgamma(used.a_rho);
+        }
+    }
+    __syncthreads();
+    if (lane != 0) return;
+    const double rho_stat = tot[S - 2];
+    if (init_mode) {
+        // initial state (Section 3.5) and the coefficients of the first pass
+        st->a_rho = pr->a0;
+        st->b_rho = pr->b0;
+        double K0K[M], W[M * M];
+        for (int i = 0; i < M; ++i) K0K[i] = 1.0 / (M + 1);
+        for (int i = 0; i < M * M; ++i) W[i] = pr->L0inv[i];
+        for (int i = 0; i < M; ++i) st->K0K[i] = K0K[i];
+        for (int i = 0; i < M * M; ++i) st->W[i] = W[i];
+        st->nu = nu;
+        st->kappa = kappa;
+        st->elbo = 0.0;
+        st->sweeps = 0;
+        st->call_sweeps = 0;
+        st->converged = 0;
+        st->swept = 0;
+        const double a1 = pr->a0 + 0.5 * V, b1 = pr->b0 + 0.5 * rho_stat;
+        st->numeric = isfinite(b1) ? 0 : 1;
+        next_coef<M>(st->coef, a1, b1, W, K0K, nu);
+        return;
+    }
+    // q(K, Lambda): eqs 24 and 25 with the new q(beta)
+    double K0K[M], Winv[M * M], W[M * M], Ebb[M * M];
+    for (int i = 0; i < M; ++i) K0K[i] = (tot[i] + pr->q0 * pr->K0[i]) / (V + pr->q0);
+    for (int i = 0; i < M; ++i)
+        for (int k = i; k < M; ++k) {
+            Ebb[i * M + k] = tot[tri(M, i, k)];
+            Ebb[k * M + i] = tot[tri(M, i, k)];
+        }
+    for (int i = 0; i < M; ++i)
+        for (int k = 0; k < M; ++k)
+            Winv[i * M + k] = pr->L0inv[i * M + k] + Ebb[i * M + k] + pr->q0 * pr->K0[i] * pr->K0[k]
+                              - (pr->q0 + V) * K0K[i] * K0K[k];
+    double lndetWinv = 0.0;
+    bool bad = !spd_inverse<M>(Winv, W, lndetWinv);
+    const double lndetW = -lndetWinv;
+    // the lower bound at q(rho) of this sweep, the new q(beta) and the new q(K, Lambda)
+    const double a = used.a_rho, b = used.b_rho;
+    const double Erho = a / b, Elnrho = sp[0][M] - log(b);
+    double sdig = 0.0, slg = 0.0;
+    for (int j = 0; j < M; ++j) {
+        sdig += sp[0][j];
+        slg += sp[1][j];
+    }
+    const double ElndetL = sdig + M * kLn2 + lndetW;
+    double trWA = 0.0, trL0W = 0.0, dKWdK = 0.0;
+    for (int i = 0; i < M; ++i)
+        for (int k = 0; k < M; ++k) {
+            const double A = Ebb[k * M + i] - tot[k] * K0K[i] - K0K[k] * tot[i] + V * K0K[k] * K0K[i];
+            trWA += W[i * M + k] * A;
+            trL0W += pr->L0inv[i * M + k] * W[k * M + i];
+            dKWdK += (K0K[i] - pr->K0[i]) * W[i * M + k] * (K0K[k] - pr->K0[k]);
+        }
+    const double t_lik = 0.5 * V * Elnrho - 0.5 * V * kLn2Pi - 0.5 * Erho * rho_stat;
+    const double t_beta = 0.5 * V * ElndetL - 0.5 * V * M * kLn2Pi - 0.5 * (nu * trWA + V * M / kappa);
+    const double t_rho = pr->a0 * log(pr->b0) - pr->lg_a0 + (pr->a0 - 1.0) * Elnrho - pr->b0 * Erho;
+    const double t_K = 0.5 * M * log(pr->q0 / (2.0 * M_PI)) + 0.5 * ElndetL - 0.5 * pr->q0 * (nu * dKWdK + M / kappa);
+    const double t_L = 0.5 * (pr->n0 - M - 1.0) * ElndetL - 0.5 * nu * trL0W + pr->lnB0;
+    const double h_rho = a - log(b) + sp[1][M] + (1.0 - a) * sp[0][M];
+    const double h_beta = 0.5 * V * M * (1.0 + kLn2Pi) - 0.5 * tot[S - 1];
+    const double h_K = -(0.5 * M * log(kappa / (2.0 * M_PI)) + 0.5 * ElndetL - 0.5 * M);
+    const double lnBW = -0.5 * nu * lndetW - 0.5 * nu * M * kLn2 - 0.25 * M * (M - 1) * kLnPi - slg;
+    const double h_L = -lnBW - 0.5 * (nu - M - 1.0) * ElndetL + 0.5 * nu * M;
+    const double L = t_lik + t_beta + t_rho + t_K + t_L + h_rho + h_beta + h_K + h_L;
+    // q(rho) for the next sweep from the new q(beta) (eqs 16, 17)
+    const double a1 = pr->a0 + 0.5 * V, b1 = pr->b0 + 0.5 * rho_stat;
+    bad = bad || !isfinite(L) || !isfinite(b1) || !(b1 > 0.0);
+    for (int i = 0; i < M; ++i) bad = bad || !isfinite(K0K[i]);
+    if (bad) {
+        st->numeric = 1;
+        return;
+    }
+    const int t = st->call_sweeps + 1;
+    if (t >= 2 && fabs(L - st->elbo) <= st->tol * fabs(L)) st->converged = 1;
+    hist[(t - 1) % kHistCap] = L;
+    st->elbo = L;
+    st->call_sweeps = t;
+    st->sweeps += 1;
+    st->a_rho = a;
+    st->b_rho = b;
+    for (int i = 0; i < M; ++i) st->K0K[i] = K0K[i];
+    for (int i = 0; i < M * M; ++i) st->W[i] = W[i];
+    st->nu = nu;
+    st->kappa = kappa;
+    st->used = used;
+    st->swept = 1;
+    next_coef<M>(st->coef, a1, b1, W, K0K, nu);
+}
+
+// The gene factors of the current state: from the coefficients of the pass that formed them, or
+// the initial values (m_i = 1/N, P_i = L0) before the first sweep.
+template <int M>
+__global__ __launch_bounds__(kThreads) void k_lm_genes(Shape sh, const double *__restrict__ r,
+                                                        const double *__restrict__ d, const State *st,
+                                                        const Prior *pr, double *m_out, double *P_out)
+{
+    constexpr int N = M + 1;
+    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (g >= sh.V) return;
+    double m[M], P[M][M];
+    if (!st->swept) {
+        for (int i = 0; i < M; ++i) {
+            m[i] = 1.0 / N;
+            for (int k = 0; k < M; ++k) P[i][k] = pr->L0[i * M + k];
+        }
+    } else {
+        const Coef &c = st->used;
+        double dv[N], D[M], Sg[M][M], detP;
+#pragma unroll
+        for (int q = 0; q < N; ++q) dv[q] = d[g * N + q];
+#pragma unroll
+        for (int q = 0; q < M; ++q) D[q] = dv[q] - dv[N - 1];
+        gene_factor<M>(D, r[g] - dv[N - 1], c, m, Sg, detP);
+        for (int i = 0; i < M; ++i)
+            for (int k = 0; k < M; ++k) P[i][k] = c.ELam[i * M + k] + c.Erho * D[i] * D[k];
+    }
+    if (m_out)
+        for (int i = 0; i < M; ++i) m_out[g * M + i] = m[i];
+    if (P_out)
+        for (int i = 0; i < M; ++i)
+            for (int k = 0; k < M; ++k) P_out[(g * M + i) * M + k] = P[i][k];
+}
+
+__global__ void k_lm_ctl(State *st, int max_call, int stop_on_conv, double tol)
+{
+    st->max_call = max_call;
+    st->stop_on_conv = stop_on_conv;
+    st->tol = tol;
+    st->call_sweeps = 0;
+    st->converged = 0;
+    st->numeric = 0;
+}
+
+cavi_status lfail(cavi_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    cavi::set_last_error(buf);
+    return s;
+}
+
+#define LCHK(expr)                                                                                 \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return lfail(CAVI_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+template <int M>
+hipError_t launch_sweep(const Shape &sh, const double *r, const double *d, State *st, const Prior *pr,
+                        double *partials, double *level1, double *hist, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_lm_pass<M, false>), dim3(sh.nchunk), dim3(kThreads), 0, s, sh, r, d, st, pr, partials);
+    hipLaunchKernelGGL(k_lm_reduce, dim3(kGroups), dim3(kRedThreads), 0, s, sh, st, 0, partials, level1);
+    hipLaunchKernelGGL((k_lm_global<M>), dim3(1), dim3(64), 0, s, sh, st, pr, 0, level1, hist);
+    return hipGetLastError();
+}
+
+template <int M>
+hipError_t launch_init(const Shape &sh, const double *r, const double *d, State *st, const Prior *pr,
+                       double *partials, double *level1, double *hist, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_lm_pass<M, true>), dim3(sh.nchunk), dim3(kThreads), 0, s, sh, r, d, st, pr, partials);
+    hipLaunchKernelGGL(k_lm_reduce, dim3(kGroups), dim3(kRedThreads), 0, s, sh, st, 1, partials, level1);
+    hipLaunchKernelGGL((k_lm_global<M>), dim3(1), dim3(64), 0, s, sh, st, pr, 1, level1, hist);
+    return hipGetLastError();
+}
+
+template <int M>
+hipError_t launch_genes(const Shape &sh, const double *r, const double *d, const State *st, const Prior *pr,
+                        double *m, double *P, hipStream_t s)
+{
+    const int64_t nb = (sh.V + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL((k_lm_genes<M>), dim3((unsigned)nb), dim3(kThreads), 0, s, sh, r, d, st, pr, m, P);
+    return hipGetLastError();
+}
+
+hipError_t sweep_M(int M, const Shape &sh, const double *r, const double *d, State *st, const Prior *pr,
+                   double *partials, double *level1, double *hist, hipStream_t s)
+{
+#define CALL(K) launch_sweep<K>(sh, r, d, st, pr, partials, level1, hist, s)
+    switch (M) {
+    case 1: return CALL(1);
+    case 2: return CALL(2);
+    case 3: return CALL(3);
+    case 4: return CALL(4);
+    case 5: return CALL(5);
+    case 6: return CALL(6);
+    default: return CALL(7);
+    }
+#undef CALL
+}
+
+hipError_t init_M(int M, const Shape &sh, const double *r, const double *d, State *st, const Prior *pr,
+                  double *partials, double *level1, double *hist, hipStream_t s)
+{
+#define CALL(K) launch_init<K>(sh, r, d, st, pr, partials, level1, hist, s)
+    switch (M) {
+    case 1: return CALL(1);
+    case 2: return CALL(2);
+    case 3: return CALL(3);
+    case 4: return CALL(4);
+    case 5: return CALL(5);
+    case 6: return CALL(6);
+    default: return CALL(7);
+    }
+#undef CALL
+}
+
+hipError_t genes_M(int M, const Shape &sh, const double *r, const double *d, const State *st, const Prior *pr,
+                   double *m, double *P, hipStream_t s)
+{
+#define CALL(K) launch_genes<K>(sh, r, d, st, pr, m, P, s)
+    switch (M) {
+    case 1: return CALL(1);
+    case 2: return CALL(2);
+    case 3: return CALL(3);
+    case 4: return CALL(4);
+    case 5: return CALL(5);
+    case 6: return CALL(6);
+    default: return CALL(7);
+    }
+#undef CALL
+}
+
+// Host Cholesky of an SPD matrix: inverse and ln det; false if not SPD.
+bool host_spd_inverse(int M, const double *A, double *Ainv, double *lndet)
+{
+    std::vector<double> L(M * M, 0.0), Li(M * M, 0.0);
+    double ld = 0.0;
+    for (int j = 0; j < M; ++j) {
+        double s = A[j * M + j];
+        for (int k = 0; k < j; ++k) s -= L[j * M + k] * L[j * M + k];
+        if (!(s > 0.0) || !isfinite(s)) return false;
+        const double ljj = sqrt(s);
+        ld += 2.0 * log(ljj);
+        L[j * M + j] = ljj;
+        for (int i = j + 1; i < M; ++i) {
+            double t = A[i * M + j];
+            if (fabs(A[i * M + j] - A[j * M + i]) > 1e-12 * (fabs(A[i * M + j]) + fabs(A[j * M + i])) + 1e-300)
+                return false;  // not symmetric
+            for (int k = 0; k < j; ++k) t -= L[i * M + k] * L[j * M + k];
+            L[i * M + j] = t / ljj;
+        }
+    }
+    for (int j = 0; j < M; ++j) {
+        Li[j * M + j] = 1.0 / L[j * M + j];
+        for (int i = j + 1; i < M; ++i) {
+            double s = 0.0;
+            for (int k = j; k < i; ++k) s -= L[i * M + k] * Li[k * M + j];
+            Li[i * M + j] = s / L[i * M + i];
+        }
+    }
+    for (int i = 0; i < M; ++i)
+        for (int j = 0; j < M; ++j) {
+            double s = 0.0;
+            for (int k = (i > j ? i : j); k < M; ++k) s += Li[k * M + i] * Li[k * M + j];
+            Ainv[i * M + j] = s;
+        }
+    if (lndet) *lndet = ld;
+    return true;
+}
+
+}  // namespace
+
+struct lmvb_ctx {
+    Shape sh{};
+    const double *r = nullptr, *d = nullptr;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    State *st = nullptr;   // device
+    Prior *pr = nullptr;   // device
+    double *partials = nullptr, *level1 = nullptr, *hist = nullptr;
+    bool ready = false;
+};
+
+extern "C" {
+
+cavi_status lmvb_create(lmvb_ctx **out, const double *r_dev, const double *d_dev, int64_t V, int32_t N,
+                        const lmvb_prior *prior, void *hip_stream)
+{
+    if (!out) return lfail(CAVI_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!r_dev || !d_dev) return lfail(CAVI_E_INVAL, "r_dev or d_dev is NULL");
+    if ((((uintptr_t)r_dev) & 7) || (((uintptr_t)d_dev) & 7)) return lfail(CAVI_E_INVAL, "r_dev or d_dev is not 8-byte aligned");
+    if (V < 1 || V >= ((int64_t)1 << 40)) return lfail(CAVI_E_INVAL, "V=%lld outside [1, 2^40)", (long long)V);
+    if (N < 2 || N > kMaxM + 1) return lfail(CAVI_E_INVAL, "N=%d outside [2, %d]", N, kMaxM + 1);
+    const int M = N - 1;
+    Prior p{};
+    if (prior) {
+        p.a0 = prior->a0;
+        p.b0 = prior->b0;
+        p.q0 = prior->q0;
+        p.n0 = prior->n0;
+        if (!prior->K0 || !prior->L0) return lfail(CAVI_E_INVAL, "prior K0 or L0 is NULL");
+        for (int i = 0; i < M; ++i) p.K0[i] = prior->K0[i];
+        for (int i = 0; i < M * M; ++i) p.L0[i] = prior->L0[i];
+    } else {
+        p.a0 = p.b0 = 0.5;
+        p.q0 = 0.001;
+        p.n0 = 1.0;
+        for (int i = 0; i < M; ++i) p.K0[i] = 1.0 / N;
+        if (M == 2) {
+            // L0 = [[0.01, 0.005], [0.005, 0.008]]^-1
+            const double A[4] = {0.01, 0.005, 0.005, 0.008};
+            host_spd_inverse(2, A, p.L0, nullptr);
+        } else {
+            for (int i = 0; i < M; ++i)
+                for (int j = 0; j < M; ++j) p.L0[i * M + j] = i == j ? 100.0 : 0.0;
+        }
+    }
+    for (double v : {p.a0, p.b0, p.q0, p.n0})
+        if (!(v > 0.0) || !isfinite(v)) return lfail(CAVI_E_INVAL, "prior a0, b0, q0, n0 must be finite and > 0");
+    for (int i = 0; i < M; ++i)
+        if (!isfinite(p.K0[i])) return lfail(CAVI_E_INVAL, "prior K0[%d] is not finite", i);
+    double lndetL0 = 0.0;
+    if (!host_spd_inverse(M, p.L0, p.L0inv, &lndetL0)) return lfail(CAVI_E_INVAL, "prior L0 is not symmetric positive definite");
+    if (!(p.n0 + (double)V > M - 1)) return lfail(CAVI_E_INVAL, "n0 + V must exceed N - 2 (a proper posterior Wishart)");
+    if (p.n0 > M - 1) {
+        double s = 0.0;
+        for (int j = 1; j <= M; ++j) s += lgamma(0.5 * (p.n0 + 1 - j));
+        p.lnB0 = -0.5 * p.n0 * lndetL0 - 0.5 * p.n0 * M * kLn2 - 0.25 * M * (M - 1) * kLnPi - s;
+    }
+    p.lg_a0 = lgamma(p.a0);
+    lmvb_ctx *h = new lmvb_ctx;
+    h->sh.V = V;
+    h->sh.N = N;
+    h->sh.M = M;
+    h->sh.nchunk = (int32_t)((V + kChunk - 1) / kChunk);
+    h->sh.S = M + M * (M + 1) / 2 + 2;
+    h->r = r_dev;
+    h->d = d_dev;
+    hipError_t e = hipSuccess;
+    if (hip_stream) {
+        h->stream = (hipStream_t)hip_stream;
+    } else {
+        e = hipStreamCreate(&h->stream);
+        if (e != hipSuccess) {
+            delete h;
+            return lfail(CAVI_E_HIP, "hipStreamCreate: %s", hipGetErrorString(e));
+        }
+        h->own_stream = true;
+    }
+    if ((e = hipMalloc(&h->st, sizeof(State))) != hipSuccess || (e = hipMalloc(&h->pr, sizeof(Prior))) != hipSuccess ||
+        (e = hipMalloc(&h->partials, sizeof(double) * (size_t)h->sh.nchunk * h->sh.S)) != hipSuccess ||
+        (e = hipMalloc(&h->level1, sizeof(double) * kGroups * kMaxS)) != hipSuccess ||
+        (e = hipMalloc(&h->hist, sizeof(double) * kHistCap)) != hipSuccess) {
+        (void)hipGetLastError();
+        lmvb_destroy(h);
+        return lfail(CAVI_E_NOMEM, "device allocation: %s", hipGetErrorString(e));
+    }
+    State s0{};
+    e = hipMemcpyAsync(h->pr, &p, sizeof(Prior), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->st, &s0, sizeof(State), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        lmvb_destroy(h);
+        return lfail(CAVI_E_HIP, "upload: %s", hipGetErrorString(e));
+    }
+    *out = h;
+    return CAVI_OK;
+}
+
+cavi_status lmvb_init(lmvb_ctx *h)
+{
+    if (!h) return lfail(CAVI_E_INVAL, "handle is NULL");
+    LCHK(init_M(h->sh.M, h->sh, h->r, h->d, h->st, h->pr, h->partials, h->level1, h->hist, h->stream));
+    State s;
+    LCHK(hipMemcpyAsync(&s, h->st, sizeof(State), hipMemcpyDeviceToHost, h->stream));
+    LCHK(hipStreamSynchronize(h->stream));
+    if (s.numeric) return lfail(CAVI_E_NUMERIC, "the initial statistic of eq 17 is not finite");
+    h->ready = true;
+    return CAVI_OK;
+}
+
+static cavi_status enqueue(lmvb_ctx *h, int n, int max_call, int stop_on_conv, double tol, bool begin)
+{
+    if (begin) hipLaunchKernelGGL(k_lm_ctl, dim3(1), dim3(1), 0, h->stream, h->st, max_call, stop_on_conv, tol);
+    for (int i = 0; i < n; ++i)
+        LCHK(sweep_M(h->sh.M, h->sh, h->r, h->d, h->st, h->pr, h->partials, h->level1, h->hist, h->stream));
+    return CAVI_OK;
+}
+
+cavi_status lmvb_sweep(lmvb_ctx *h, int32_t n, double *elbo_host)
+{
+    if (!h) return lfail(CAVI_E_INVAL, "handle is NULL");
+    if (!h->ready) return lfail(CAVI_E_STATE, "lmvb_init has not run");
+    if (n < 1 || n > kHistCap) return lfail(CAVI_E_INVAL, "n=%d outside [1, %d]", n, kHistCap);
+    cavi_status st = enqueue(h, n, n, 0, 0.0, true);
+    if (st != CAVI_OK) return st;
+    State s;
+    LCHK(hipMemcpyAsync(&s, h->st, sizeof(State), hipMemcpyDeviceToHost, h->stream));
+    if (elbo_host) LCHK(hipMemcpyAsync(elbo_host, h->hist, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+    LCHK(hipStreamSynchronize(h->stream));
+    if (s.numeric) return lfail(CAVI_E_NUMERIC, "sweep %d produced a non-finite value", s.call_sweeps + 1);
+    return CAVI_OK;
+}
+
+cavi_status lmvb_run(lmvb_ctx *h, int32_t max_sweeps, double rel_tol, int32_t *sweeps, double *elbo)
+{
+    if (!h) return lfail(CAVI_E_INVAL, "handle is NULL");
+    if (!h->ready) return lfail(CAVI_E_STATE, "lmvb_init has not run");
+    if (max_sweeps < 1) return lfail(CAVI_E_INVAL, "max_sweeps=%d < 1", max_sweeps);
+    if (!(rel_tol >= 0.0) || !isfinite(rel_tol)) return lfail(CAVI_E_INVAL, "rel_tol must be finite and >= 0");
+    State s{};
+    int done = 0, batch = 16;
+    bool first = true;
+    while (true) {
+        const int n = std::min(batch, max_sweeps - done);
+        cavi_status st = enqueue(h, n, max_sweeps, 1, rel_tol, first);
+        if (st != CAVI_OK) return st;
+        first = false;
+        done += n;
+        LCHK(hipMemcpyAsync(&s, h->st, sizeof(State), hipMemcpyDeviceToHost, h->stream));
+        LCHK(hipStreamSynchronize(h->stream));
+        if (s.numeric || s.converged || done >= max_sweeps) break;
+        batch = std::min(batch * 2, 256);
+    }
+    if (sweeps) *sweeps = s.call_sweeps;
+    if (elbo) *elbo = s.elbo;
+    if (s.numeric) return lfail(CAVI_E_NUMERIC, "sweep %d produced a non-finite value", s.call_sweeps + 1);
+    if (!s.converged) return lfail(CAVI_E_NOTCONV, "not converged after %d sweeps", s.call_sweeps);
+    return CAVI_OK;
+}
+
+cavi_status lmvb_get_globals(lmvb_ctx *h, double *a_rho, double *b_rho, double *K0K, double *W, double *nu,
+                             double *kappa)
+{
+    if (!h) return lfail(CAVI_E_INVAL, "handle is NULL");
+    if (!h->ready) return lfail(CAVI_E_STATE, "lmvb_init has not run");
+    State s;
+    LCHK(hipMemcpyAsync(&s, h->st, sizeof(State), hipMemcpyDeviceToHost, h->stream));
+    LCHK(hipStreamSynchronize(h->stream));
+    const int M = h->sh.M;
+    if (a_rho) *a_rho = s.a_rho;
+    if (b_rho) *b_rho = s.b_rho;
+    if (K0K)
+        for (int i = 0; i < M; ++i) K0K[i] = s.K0K[i];
+    if (W)
+        for (int i = 0; i < M * M; ++i) W[i] = s.W[i];
+    if (nu) *nu = s.nu;
+    if (kappa) *kappa = s.kappa;
+    return CAVI_OK;
+}
+
+cavi_status lmvb_get_genes(lmvb_ctx *h, double *m_dev, double *P_dev)
+{
+    if (!h) return lfail(CAVI_E_INVAL, "handle is NULL");
+    if (!h->ready) return lfail(CAVI_E_STATE, "lmvb_init has not run");
+    if ((((uintptr_t)m_dev) & 7) || (((uintptr_t)P_dev) & 7)) return lfail(CAVI_E_INVAL, "outputs must be 8-byte aligned");
+    LCHK(genes_M(h->sh.M, h->sh, h->r, h->d, h->st, h->pr, m_dev, P_dev, h->stream));
+    LCHK(hipStreamSynchronize(h->stream));
+    return CAVI_OK;
+}
+
+cavi_status lmvb_destroy(lmvb_ctx *h)
+{
+    if (!h) return CAVI_OK;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->st) (void)hipFree(h->st);
+    if (h->pr) (void)hipFree(h->pr);
+    if (h->partials) (void)hipFree(h->partials);
+    if (h->level1) (void)hipFree(h->level1);
+    if (h->hist) (void)hipFree(h->hist);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+    return CAVI_OK;
+}
+
+}  // extern "C"

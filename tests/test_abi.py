@@ -103,3 +103,44 @@ def test_warm_start_and_schedule_entry_points_reject_bad_arguments(L):
     assert L.cavi_get_schedule(None, None, None) == cavi.CAVI_E_INVAL
     assert L.cavi_batch_set_schedule(None, 1) == cavi.CAVI_E_INVAL
     assert L.cavi_batch_get_schedule(None, None, None) == cavi.CAVI_E_INVAL
+
+
+def test_lmvb_symbols_exported_and_argument_checks(L):
+    """include/lmvb.h: every declared entry point is exported; shape, pointer, alignment and prior
+    checks return CAVI_E_INVAL before any device call."""
+    from paper_2401_10068_amd import lmvb
+
+    text = open(os.path.join(ROOT, "include", "lmvb.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = sorted(set(re.findall(r"\b(lmvb_[a-z0-9_]+)\s*\(", text)))
+    assert len(names) == 7, names
+    LL = lmvb.lib()
+    for n in names:
+        assert hasattr(LL, n), n
+
+    def create(r, d, V, N, prior=None):
+        h = C.c_void_p()
+        return LL.lmvb_create(C.byref(h), C.c_void_p(r), C.c_void_p(d), V, N, C.byref(prior) if prior else None, None)
+
+    ok = 1 << 20  # any aligned non-NULL address: the checks below fail before it is used
+    for r, d, V, N in [(0, ok, 10, 3), (ok, 0, 10, 3), (ok + 4, ok, 10, 3), (ok, ok + 1, 10, 3), (ok, ok, 0, 3),
+                       (ok, ok, 10, 1), (ok, ok, 10, 9), (ok, ok, 1 << 40, 3)]:
+        assert create(r, d, V, N) == cavi.CAVI_E_INVAL, (r, d, V, N)
+    import numpy as np
+
+    K0 = np.array([0.3, 0.3])
+    bad_L0 = np.array([[1.0, 2.0], [2.0, 1.0]])  # not positive definite
+    asym_L0 = np.array([[2.0, 0.5], [0.1, 2.0]])
+    good_L0 = np.eye(2)
+    for a0, b0, q0, n0, L0 in [(0.5, 0.5, 0.001, 1.0, bad_L0), (0.5, 0.5, 0.001, 1.0, asym_L0),
+                               (-1.0, 0.5, 0.001, 1.0, good_L0), (0.5, 0.0, 0.001, 1.0, good_L0),
+                               (0.5, 0.5, float("nan"), 1.0, good_L0)]:
+        pr = lmvb.lmvb_prior(a0, b0, q0, n0, cavi._dp(K0), cavi._dp(np.ascontiguousarray(L0)))
+        assert create(ok, ok, 10, 3, pr) == cavi.CAVI_E_INVAL, (a0, b0, q0, n0, L0)
+    # n0 + V must exceed N - 2: V = 1, N = 8 with n0 = 1 gives 2 <= 6
+    K7 = np.full(7, 0.125)
+    pr = lmvb.lmvb_prior(0.5, 0.5, 0.001, 1.0, cavi._dp(K7), cavi._dp(np.eye(7)))
+    assert create(ok, ok, 1, 8, pr) == cavi.CAVI_E_INVAL
+    assert LL.lmvb_init(None) == cavi.CAVI_E_INVAL
+    assert LL.lmvb_sweep(None, 1, None) == cavi.CAVI_E_INVAL
+    assert LL.lmvb_destroy(None) == cavi.CAVI_OK
