@@ -79,6 +79,10 @@ cavi_status lmvb_get_globals(lmvb_ctx *h, double *a_rho, double *b_rho, double *
  * P_dev (V x M x M).  Enqueued on the handle's stream; synchronises. */
 cavi_status lmvb_get_genes(lmvb_ctx *h, double *m_dev, double *P_dev);
 
+/* Average duration (ms, HIP events on the handle's stream) of reps launches of the per-gene pass
+ * with the current coefficients (the state is unchanged).  Synchronises. */
+cavi_status lmvb_profile_pass(lmvb_ctx *h, int32_t reps, float *ms);
+
 /* Release the handle (NULL is a no-op). */
 cavi_status lmvb_destroy(lmvb_ctx *h);
 

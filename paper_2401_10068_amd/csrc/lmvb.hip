@@ -90,12 +90,36 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// q(beta_i) of one gene: P = E[Lambda] + E[rho] D D^T (eq 20) factored as L L^T, the mean
-// m = P^-1 (E[Lambda K] + E[rho] D e) (eq 21, e = r - mu), S = P^-1 = L^-T L^-1 and det P.
+// q(beta_i) of one gene: P = E[Lambda] + E[rho] D D^T (eq 20), the mean
+// m = P^-1 (E[Lambda K] + E[rho] D e) (eq 21, e = r - mu), S = P^-1 and det P.  M = 1 and 2 use
+// the closed-form inverse (one division); larger M factor P = L L^T, S = L^-T L^-1.
 template <int M>
 __device__ __forceinline__ void gene_factor(const double (&D)[M], double e, const Coef &c, double (&m)[M],
                                             double (&S)[M][M], double &detP)
 {
+    if constexpr (M == 1) {
+        const double p = c.ELam[0] + c.Erho * D[0] * D[0];
+        const double ip = 1.0 / p;
+        S[0][0] = ip;
+        m[0] = (c.ELamK[0] + c.Erho * D[0] * e) * ip;
+        detP = p;
+        return;
+    }
+    if constexpr (M == 2) {
+        const double p00 = c.ELam[0] + c.Erho * D[0] * D[0];
+        const double p01 = c.ELam[1] + c.Erho * D[0] * D[1];
+        const double p11 = c.ELam[3] + c.Erho * D[1] * D[1];
+        const double det = fma(p00, p11, -p01 * p01);
+        const double id = 1.0 / det;
+        S[0][0] = p11 * id;
+        S[1][1] = p00 * id;
+        S[0][1] = S[1][0] = -p01 * id;
+        const double b0 = c.ELamK[0] + c.Erho * D[0] * e, b1 = c.ELamK[1] + c.Erho * D[1] * e;
+        m[0] = (p11 * b0 - p01 * b1) * id;
+        m[1] = (p00 * b1 - p01 * b0) * id;
+        detP = det;
+        return;
+    }
     double L[M][M], Li[M][M], y[M];
 #pragma unroll
     for (int i = 0; i < M; ++i)
@@ -156,8 +180,9 @@ __device__ __forceinline__ void gene_factor(const double (&D)[M], double e, cons
 }
 
 // One thread per gene.  Per chunk: [sum m (M) | sum E[beta beta^T] (upper triangle, row-major) |
-// sum of the eq 17 bracket | sum ln det P_i], each summed per thread over its genes in order,
-// then over the wave's lanes by a fixed butterfly, then over the four waves in order.
+// sum of the eq 17 bracket | sum ln det P_i], each summed per thread over its genes in order (the
+// log determinants as the log of their product, kept as mantissa and exponent), then over the
+// wave's lanes by a fixed butterfly, then over the four waves in order.
 // INIT: the gene factors of the initial state (m_i = 1/N, P_i = L0) instead of the coefficients.
 template <int M, bool INIT>
 __global__ __launch_bounds__(kThreads) void k_lm_pass(Shape sh, const double *__restrict__ r,
@@ -178,6 +203,9 @@ __global__ __launch_bounds__(kThreads) void k_lm_pass(Shape sh, const double *__
     double acc[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) acc[s] = 0.0;
+    // product of the thread's det P_i as mantissa and binary exponent: one log per thread
+    double dmant = 1.0;
+    int dexp = 0;
     const int64_t g0 = (int64_t)blockIdx.x * kChunk + threadIdx.x;
     for (int j = 0; j < kPerThread; ++j) {
         const int64_t g = g0 + (int64_t)j * kThreads;
@@ -216,8 +244,14 @@ __global__ __launch_bounds__(kThreads) void k_lm_pass(Shape sh, const double *__
                 quad += (i == k ? 1.0 : 2.0) * D[i] * ebb * D[k];
             }
         acc[S - 2] += e * e - 2.0 * e * Dm + quad;
-        acc[S - 1] += INIT ? 0.0 : log(detP);
+        if (!INIT) {
+            int e1, e2;
+            const double f = frexp(detP, &e1);
+            dmant = frexp(dmant * f, &e2);
+            dexp += e1 + e2;
+        }
     }
+    acc[S - 1] = INIT ? 0.0 : log(dmant) + dexp * kLn2;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -545,6 +579,30 @@ hipError_t sweep_M(int M, const Shape &sh, const double *r, const double *d, Sta
 #undef CALL
 }
 
+template <int M>
+hipError_t launch_pass(const Shape &sh, const double *r, const double *d, State *st, const Prior *pr,
+                       double *partials, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_lm_pass<M, false>), dim3(sh.nchunk), dim3(kThreads), 0, s, sh, r, d, st, pr, partials);
+    return hipGetLastError();
+}
+
+hipError_t pass_M(int M, const Shape &sh, const double *r, const double *d, State *st, const Prior *pr,
+                  double *partials, hipStream_t s)
+{
+#define CALL(K) launch_pass<K>(sh, r, d, st, pr, partials, s)
+    switch (M) {
+    case 1: return CALL(1);
+    case 2: return CALL(2);
+    case 3: return CALL(3);
+    case 4: return CALL(4);
+    case 5: return CALL(5);
+    case 6: return CALL(6);
+    default: return CALL(7);
+    }
+#undef CALL
+}
+
 hipError_t init_M(int M, const Shape &sh, const double *r, const double *d, State *st, const Prior *pr,
                   double *partials, double *level1, double *hist, hipStream_t s)
 {
@@ -804,6 +862,29 @@ cavi_status lmvb_get_genes(lmvb_ctx *h, double *m_dev, double *P_dev)
     if ((((uintptr_t)m_dev) & 7) || (((uintptr_t)P_dev) & 7)) return lfail(CAVI_E_INVAL, "outputs must be 8-byte aligned");
     LCHK(genes_M(h->sh.M, h->sh, h->r, h->d, h->st, h->pr, m_dev, P_dev, h->stream));
     LCHK(hipStreamSynchronize(h->stream));
+    return CAVI_OK;
+}
+
+cavi_status lmvb_profile_pass(lmvb_ctx *h, int32_t reps, float *ms)
+{
+    if (!h || !ms) return lfail(CAVI_E_INVAL, "handle or ms is NULL");
+    if (!h->ready) return lfail(CAVI_E_STATE, "lmvb_init has not run");
+    if (reps < 1) return lfail(CAVI_E_INVAL, "reps=%d < 1", reps);
+    hipEvent_t e0, e1;
+    LCHK(hipEventCreate(&e0));
+    LCHK(hipEventCreate(&e1));
+    // one sweep allowed, so that the pass is not skipped; the pass only writes the chunk sums,
+    // which the next sweep overwrites
+    hipLaunchKernelGGL(k_lm_ctl, dim3(1), dim3(1), 0, h->stream, h->st, 1, 0, 0.0);
+    LCHK(hipEventRecord(e0, h->stream));
+    for (int i = 0; i < reps; ++i) LCHK(pass_M(h->sh.M, h->sh, h->r, h->d, h->st, h->pr, h->partials, h->stream));
+    LCHK(hipEventRecord(e1, h->stream));
+    LCHK(hipEventSynchronize(e1));
+    float t = 0.f;
+    LCHK(hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = t / (float)reps;
     return CAVI_OK;
 }
 

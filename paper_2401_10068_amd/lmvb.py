@@ -32,6 +32,7 @@ def lib():
             "lmvb_run": (st, [vp, C.c_int32, C.c_double, C.POINTER(C.c_int32), dp]),
             "lmvb_get_globals": (st, [vp, dp, dp, dp, dp, dp, dp]),
             "lmvb_get_genes": (st, [vp, vp, vp]),
+            "lmvb_profile_pass": (st, [vp, C.c_int32, C.POINTER(C.c_float)]),
             "lmvb_destroy": (st, [vp]),
         }
         for name, (res, args) in sig.items():
@@ -99,6 +100,12 @@ class LinMixVB:
         P = torch.empty((self.V, self.M, self.M), dtype=torch.float64, device=dev)
         _cavi._check(lib().lmvb_get_genes(self.h, C.c_void_p(m.data_ptr()), C.c_void_p(P.data_ptr())))
         return m, P
+
+    def profile_pass(self, reps: int = 20) -> float:
+        """Average duration (ms) of the per-gene pass kernel."""
+        ms = C.c_float()
+        _cavi._check(lib().lmvb_profile_pass(self.h, reps, C.byref(ms)))
+        return ms.value
 
     def close(self):
         if getattr(self, "h", None):

@@ -113,7 +113,7 @@ def test_lmvb_symbols_exported_and_argument_checks(L):
     text = open(os.path.join(ROOT, "include", "lmvb.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = sorted(set(re.findall(r"\b(lmvb_[a-z0-9_]+)\s*\(", text)))
-    assert len(names) == 7, names
+    assert len(names) == 8, names
     LL = lmvb.lib()
     for n in names:
         assert hasattr(LL, n), n
