@@ -23,9 +23,10 @@
  *   - Host arrays are FP64 and caller-owned; matrices are M x M row-major.
  *   - Work runs on the stream given at creation (hipStream_t as void*; NULL: a blocking stream of
  *     the handle's own).  Functions returning results to the host synchronise it.  A handle is not
- *     thread-safe.  The library allocates its own device memory (O(V / 8192) doubles).
+ *     thread-safe.  The library allocates its own device memory (O(V / 256) doubles at most).
  *   - Determinism: results are bitwise reproducible run to run; sums over genes are defined over
- *     fixed 8192-gene chunks combined in a fixed order.
+ *     chunks of 256 p consecutive genes, p = min(32, max(1, ceil(V / 2^18))), combined in a fixed
+ *     order.
  *   - Limits: 1 <= V < 2^40, 2 <= N <= 8, n0 + V > N - 2.
  */
 #ifndef LMVB_H

@@ -6,7 +6,9 @@
 //   k_lm_pass<M>     one thread per gene: q(beta_i) from the current coefficients (eqs 20, 21),
 //                    its moments (eqs 26, 27), and the gene's terms of the sums that the global
 //                    updates need (sum m_i, sum E[beta_i beta_i^T], the bracket of eq 17 and
-//                    ln|P_i|); FP64 sums per 8192-gene chunk in a fixed order;
+//                    ln|P_i|); FP64 sums per chunk of 256 ppt genes in a fixed order, with
+//                    ppt = min(32, max(1, ceil(V / 2^18))) genes per thread (a function of V only:
+//                    small problems spread over more workgroups);
 //   k_lm_reduce      the chunk sums in 16 contiguous groups, each in chunk order;
 //   k_lm_global<M>   the groups in order, then q(K, Lambda) (eqs 24, 25), the lower bound, the
 //                    convergence test, and q(rho) (eqs 16, 17) with the coefficients E[rho],
@@ -32,8 +34,7 @@ namespace {
 
 constexpr int kMaxM = 7;
 constexpr int kThreads = 256;
-constexpr int kPerThread = 32;
-constexpr int kChunk = kThreads * kPerThread;              // genes per chunk
+constexpr int kPerThreadMax = 32;                           // genes per thread at most
 constexpr int kMaxS = kMaxM + kMaxM * (kMaxM + 1) / 2 + 2;  // sums per chunk
 constexpr int kGroups = 16;                                 // first-level reduction groups
 constexpr int kRedThreads = 1024;
@@ -73,6 +74,7 @@ struct State {
 struct Shape {
     int64_t V;
     int32_t N, M, nchunk, S;
+    int32_t ppt;  // genes per thread: a chunk is kThreads * ppt consecutive genes
 };
 
 // position of E[beta beta^T]_{ik} (i <= k) in a chunk's sums: after the M means, row-major upper triangle
@@ -206,8 +208,8 @@ __global__ __launch_bounds__(kThreads) void k_lm_pass(Shape sh, const double *__
     // product of the thread's det P_i as mantissa and binary exponent: one log per thread
     double dmant = 1.0;
     int dexp = 0;
-    const int64_t g0 = (int64_t)blockIdx.x * kChunk + threadIdx.x;
-    for (int j = 0; j < kPerThread; ++j) {
+    const int64_t g0 = (int64_t)blockIdx.x * kThreads * sh.ppt + threadIdx.x;
+    for (int j = 0; j < sh.ppt; ++j) {
         const int64_t g = g0 + (int64_t)j * kThreads;
         if (g >= sh.V) break;
         double dv[N];
@@ -738,7 +740,9 @@ cavi_status lmvb_create(lmvb_ctx **out, const double *r_dev, const double *d_dev
     h->sh.V = V;
     h->sh.N = N;
     h->sh.M = M;
-    h->sh.nchunk = (int32_t)((V + kChunk - 1) / kChunk);
+    h->sh.ppt = (int32_t)std::min<int64_t>(kPerThreadMax, std::max<int64_t>(1, (V + (1 << 18) - 1) >> 18));
+    const int64_t chunk = (int64_t)kThreads * h->sh.ppt;
+    h->sh.nchunk = (int32_t)((V + chunk - 1) / chunk);
     h->sh.S = M + M * (M + 1) / 2 + 2;
     h->r = r_dev;
     h->d = d_dev;

@@ -146,8 +146,8 @@ TABLE1 = [((0.1, 0.3), (0.1031, 0.2992)), ((0.13, 0.25), (0.1218, 0.2351)), ((0.
 
 def test_table1_weights_recovered():
     errs = []
-    for (k_true, k_paper) in TABLE1:
-        r, d = synth.linmix_dataset(1, 8000, k_true)
+    for row, (k_true, k_paper) in enumerate(TABLE1):
+        r, d = synth.linmix_dataset(1 + row, 8000, k_true)  # fresh genes for every row, as in the paper
         pr = lo.default_prior(3)
         s, _ = lo.run(r, d, pr, 100)  # the paper's VB converged in 100 iterations
         err = float(np.linalg.norm(s.K0K - np.array(k_true)))
