@@ -15,7 +15,8 @@
 //                    E[Lambda], E[Lambda K] (eqs 28, 29, 31) of the next pass.
 // The gene factors are not stored: they are a function of the data and of the coefficients of the
 // pass that formed them, which the state keeps (lmvb_get_genes recomputes them).
-// Everything is FP64, as in the paper.
+// Everything is FP64, as in the paper.  k_lm_pass and k_lm_reduce are shared with the EM
+// (linmix.h).
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -29,36 +30,9 @@
 #include "../../include/lmvb.h"
 #include "cavi_impl.h"
 #include "devmath.h"
+#include "linmix.h"
 
 namespace {
-
-constexpr int kMaxM = 7;
-constexpr int kThreads = 256;
-constexpr int kPerThreadMax = 32;                           // genes per thread at most
-constexpr int kMaxS = kMaxM + kMaxM * (kMaxM + 1) / 2 + 2;  // sums per chunk
-constexpr int kGroups = 16;                                 // first-level reduction groups
-constexpr int kRedThreads = 1024;
-constexpr int kHistCap = 1 << 16;
-constexpr double kLn2Pi = 1.8378770664093454835606594728112;
-constexpr double kLnPi = 1.1447298858494001741434273513531;
-constexpr double kLn2 = 0.69314718055994530941723212145818;
-
-// Coefficients of one pass over the genes (the current q(rho) and q(K, Lambda) through their
-// expectations), together with the q(rho) they came from.
-struct Coef {
-    double a_rho, b_rho, Erho;
-    double ELam[kMaxM * kMaxM];
-    double ELamK[kMaxM];
-};
-
-struct Prior {
-    double a0, b0, q0, n0;
-    double K0[kMaxM];
-    double L0[kMaxM * kMaxM];
-    double L0inv[kMaxM * kMaxM];
-    double lnB0;       // ln of the Wishart prior's normaliser (0 when the prior is improper)
-    double lg_a0;      // lgamma(a0)
-};
 
 struct State {
     double a_rho, b_rho;   // q(rho)
@@ -70,271 +44,6 @@ struct State {
     Coef coef;  // next pass
     Coef used;  // the pass that formed the current q(beta)
 };
-
-struct Shape {
-    int64_t V;
-    int32_t N, M, nchunk, S;
-    int32_t ppt;  // genes per thread: a chunk is kThreads * ppt consecutive genes
-};
-
-// position of E[beta beta^T]_{ik} (i <= k) in a chunk's sums: after the M means, row-major upper triangle
-__host__ __device__ constexpr int tri(int M, int i, int k) { return M + i * M - i * (i - 1) / 2 + (k - i); }
-
-__device__ __forceinline__ bool skipped(const State *s)
-{
-    return s->numeric || s->call_sweeps >= s->max_call || (s->stop_on_conv && s->converged);
-}
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// q(beta_i) of one gene: P = E[Lambda] + E[rho] D D^T (eq 20), the mean
-// m = P^-1 (E[Lambda K] + E[rho] D e) (eq 21, e = r - mu), S = P^-1 and det P.  M = 1 and 2 use
-// the closed-form inverse (one division); larger M factor P = L L^T, S = L^-T L^-1.
-template <int M>
-__device__ __forceinline__ void gene_factor(const double (&D)[M], double e, const Coef &c, double (&m)[M],
-                                            double (&S)[M][M], double &detP)
-{
-    if constexpr (M == 1) {
-        const double p = c.ELam[0] + c.Erho * D[0] * D[0];
-        const double ip = 1.0 / p;
-        S[0][0] = ip;
-        m[0] = (c.ELamK[0] + c.Erho * D[0] * e) * ip;
-        detP = p;
-        return;
-    }
-    if constexpr (M == 2) {
-        const double p00 = c.ELam[0] + c.Erho * D[0] * D[0];
-        const double p01 = c.ELam[1] + c.Erho * D[0] * D[1];
-        const double p11 = c.ELam[3] + c.Erho * D[1] * D[1];
-        const double det = fma(p00, p11, -p01 * p01);
-        const double id = 1.0 / det;
-        S[0][0] = p11 * id;
-        S[1][1] = p00 * id;
-        S[0][1] = S[1][0] = -p01 * id;
-        const double b0 = c.ELamK[0] + c.Erho * D[0] * e, b1 = c.ELamK[1] + c.Erho * D[1] * e;
-        m[0] = (p11 * b0 - p01 * b1) * id;
-        m[1] = (p00 * b1 - p01 * b0) * id;
-        detP = det;
-        return;
-    }
-    double L[M][M], Li[M][M], y[M];
-#pragma unroll
-    for (int i = 0; i < M; ++i)
-#pragma unroll
-        for (int j = 0; j <= i; ++j) L[i][j] = c.ELam[i * M + j] + c.Erho * D[i] * D[j];
-    detP = 1.0;
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-        double s = L[j][j];
-#pragma unroll
-        for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
-        detP *= s;
-        const double ljj = sqrt(s);
-        L[j][j] = ljj;
-        Li[j][j] = 1.0 / ljj;
-#pragma unroll
-        for (int i = j + 1; i < M; ++i) {
-            double t = L[i][j];
-#pragma unroll
-            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
-            L[i][j] = t * Li[j][j];
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-        double s = c.ELamK[i] + c.Erho * D[i] * e;
-#pragma unroll
-        for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
-        y[i] = s * Li[i][i];
-    }
-#pragma unroll
-    for (int i = M - 1; i >= 0; --i) {
-        double s = y[i];
-#pragma unroll
-        for (int k = i + 1; k < M; ++k) s -= L[k][i] * m[k];
-        m[i] = s * Li[i][i];
-    }
-    // L^-1, lower triangular, by columns
-#pragma unroll
-    for (int j = 0; j < M; ++j)
-#pragma unroll
-        for (int i = j + 1; i < M; ++i) {
-            double s = 0.0;
-#pragma unroll
-            for (int k = j; k < i; ++k) s -= L[i][k] * Li[k][j];
-            Li[i][j] = s * Li[i][i];
-        }
-#pragma unroll
-    for (int i = 0; i < M; ++i)
-#pragma unroll
-        for (int j = i; j < M; ++j) {
-            double s = 0.0;
-#pragma unroll
-            for (int k = j; k < M; ++k) s += Li[k][i] * Li[k][j];
-            S[i][j] = s;
-            S[j][i] = s;
-        }
-}
-
-// One thread per gene.  Per chunk: [sum m (M) | sum E[beta beta^T] (upper triangle, row-major) |
-// sum of the eq 17 bracket | sum ln det P_i], each summed per thread over its genes in order (the
-// log determinants as the log of their product, kept as mantissa and exponent), then over the
-// wave's lanes by a fixed butterfly, then over the four waves in order.
-// INIT: the gene factors of the initial state (m_i = 1/N, P_i = L0) instead of the coefficients.
-template <int M, bool INIT>
-__global__ __launch_bounds__(kThreads) void k_lm_pass(Shape sh, const double *__restrict__ r,
-                                                       const double *__restrict__ d, const State *st,
-                                                       const Prior *pr, double *__restrict__ partials)
-{
-    constexpr int N = M + 1, S = M + M * (M + 1) / 2 + 2;
-    if (!INIT && skipped(st)) return;
-    __shared__ double red[kThreads / 64][S];
-    const Coef c = st->coef;
-    double Sinit[M][M];
-    if (INIT) {
-#pragma unroll
-        for (int i = 0; i < M; ++i)
-#pragma unroll
-            for (int j = 0; j < M; ++j) Sinit[i][j] = pr->L0inv[i * M + j];
-    }
-    double acc[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) acc[s] = 0.0;
-    // product of the thread's det P_i as mantissa and binary exponent: one log per thread
-    double dmant = 1.0;
-    int dexp = 0;
-    const int64_t g0 = (int64_t)blockIdx.x * kThreads * sh.ppt + threadIdx.x;
-    for (int j = 0; j < sh.ppt; ++j) {
-        const int64_t g = g0 + (int64_t)j * kThreads;
-        if (g >= sh.V) break;
-        double dv[N];
-#pragma unroll
-        for (int q = 0; q < N; ++q) dv[q] = d[g * N + q];
-        const double e = r[g] - dv[N - 1];  // r_i - mu_i
-        double D[M], m[M], Sg[M][M];
-#pragma unroll
-        for (int q = 0; q < M; ++q) D[q] = dv[q] - dv[N - 1];
-        double detP = 1.0;
-        if (INIT) {
-#pragma unroll
-            for (int i = 0; i < M; ++i) {
-                m[i] = 1.0 / N;
-#pragma unroll
-                for (int k = 0; k < M; ++k) Sg[i][k] = Sinit[i][k];
-            }
-        } else {
-            gene_factor<M>(D, e, c, m, Sg, detP);
-        }
-        // E[beta beta^T] = m m^T + S (eq 27) and the bracket of eq 17
-        double Dm = 0.0, quad = 0.0;
-#pragma unroll
-        for (int i = 0; i < M; ++i) {
-            acc[i] += m[i];
-            Dm += D[i] * m[i];
-        }
-#pragma unroll
-        for (int i = 0; i < M; ++i)
-#pragma unroll
-            for (int k = i; k < M; ++k) {
-                const double ebb = m[i] * m[k] + Sg[i][k];
-                acc[tri(M, i, k)] += ebb;
-                quad += (i == k ? 1.0 : 2.0) * D[i] * ebb * D[k];
-            }
-        acc[S - 2] += e * e - 2.0 * e * Dm + quad;
-        if (!INIT) {
-            int e1, e2;
-            const double f = frexp(detP, &e1);
-            dmant = frexp(dmant * f, &e2);
-            dexp += e1 + e2;
-        }
-    }
-    acc[S - 1] = INIT ? 0.0 : log(dmant) + dexp * kLn2;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        const double w = wave_sum(acc[s]);
-        if (lane == 0) red[wv][s] = w;
-    }
-    __syncthreads();
-    if (threadIdx.x < S) {
-        double t = red[0][threadIdx.x];
-#pragma unroll
-        for (int w = 1; w < kThreads / 64; ++w) t += red[w][threadIdx.x];
-        partials[(size_t)blockIdx.x * S + threadIdx.x] = t;
-    }
-}
-
-// Group b sums chunks [b n / 16, (b + 1) n / 16): wave v a contiguous 1/16 of them in chunk order
-// (eight loads in flight), then the 16 waves in order.  Lane s holds sum s.
-__global__ __launch_bounds__(kRedThreads) void k_lm_reduce(Shape sh, const State *st, int init_mode,
-                                                          const double *__restrict__ partials,
-                                                          double *__restrict__ level1)
-{
-    if (!init_mode && skipped(st)) return;
-    __shared__ double part[kRedThreads / 64][64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = kRedThreads / 64;
-    const int b = blockIdx.x;
-    const int c0 = (int)(((int64_t)sh.nchunk * b) / kGroups), c1 = (int)(((int64_t)sh.nchunk * (b + 1)) / kGroups);
-    const int w0 = c0 + (int)(((int64_t)(c1 - c0) * wv) / nw), w1 = c0 + (int)(((int64_t)(c1 - c0) * (wv + 1)) / nw);
-    const int s = min(lane, sh.S - 1);
-    double acc = 0.0;
-    for (int c = w0; c < w1; c += 8) {
-        double v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = partials[(size_t)min(c + j, w1 - 1) * sh.S + s];
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-            if (c + j < w1) acc += v[j];
-    }
-    part[wv][lane] = acc;
-    __syncthreads();
-    if (wv == 0 && lane < sh.S) {
-        double t = part[0][lane];
-        for (int w = 1; w < nw; ++w) t += part[w][lane];
-        level1[(size_t)b * kMaxS + lane] = t;
-    }
-}
-
-// Cholesky factor of an SPD M x M matrix (row-major), its inverse and ln det; false if not SPD.
-template <int M>
-__device__ bool spd_inverse(const double *A, double *Ainv, double &lndet)
-{
-    double L[M][M], Li[M][M];
-    lndet = 0.0;
-    for (int j = 0; j < M; ++j) {
-        double s = A[j * M + j];
-        for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
-        if (!(s > 0.0)) return false;
-        const double ljj = sqrt(s);
-        lndet += 2.0 * log(ljj);
-        L[j][j] = ljj;
-        Li[j][j] = 1.0 / ljj;
-        for (int i = j + 1; i < M; ++i) {
-            double t = A[i * M + j];
-            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
-            L[i][j] = t * Li[j][j];
-        }
-    }
-    for (int j = 0; j < M; ++j)
-        for (int i = j + 1; i < M; ++i) {
-            double s = 0.0;
-            for (int k = j; k < i; ++k) s -= L[i][k] * Li[k][j];
-            Li[i][j] = s * Li[i][i];
-        }
-    for (int i = 0; i < M; ++i)
-        for (int j = i; j < M; ++j) {
-            double s = 0.0;
-            for (int k = j; k < M; ++k) s += Li[k][i] * Li[k][j];
-            Ainv[i * M + j] = s;
-            Ainv[j * M + i] = s;
-        }
-    return true;
-}
 
 // Coefficients of the next pass from q(rho) = Gamma(a, b) and q(K, Lambda) (eqs 28, 29, 31).
 template <int M>
@@ -519,29 +228,13 @@ __global__ void k_lm_ctl(State *st, int max_call, int stop_on_conv, double tol)
     st->numeric = 0;
 }
 
-cavi_status lfail(cavi_status s, const char *fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    cavi::set_last_error(buf);
-    return s;
-}
-
-#define LCHK(expr)                                                                                 \
-    do {                                                                                           \
-        hipError_t e_ = (expr);                                                                    \
-        if (e_ != hipSuccess) return lfail(CAVI_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));   \
-    } while (0)
 
 template <int M>
 hipError_t launch_sweep(const Shape &sh, const double *r, const double *d, State *st, const Prior *pr,
                         double *partials, double *level1, double *hist, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_lm_pass<M, false>), dim3(sh.nchunk), dim3(kThreads), 0, s, sh, r, d, st, pr, partials);
-    hipLaunchKernelGGL(k_lm_reduce, dim3(kGroups), dim3(kRedThreads), 0, s, sh, st, 0, partials, level1);
+    hipLaunchKernelGGL((k_lm_pass<M, false, State>), dim3(sh.nchunk), dim3(kThreads), 0, s, sh, r, d, st, pr, partials);
+    hipLaunchKernelGGL(k_lm_reduce<State>, dim3(kGroups), dim3(kRedThreads), 0, s, sh, st, 0, partials, level1);
     hipLaunchKernelGGL((k_lm_global<M>), dim3(1), dim3(64), 0, s, sh, st, pr, 0, level1, hist);
     return hipGetLastError();
 }
@@ -550,8 +243,8 @@ template <int M>
 hipError_t launch_init(const Shape &sh, const double *r, const double *d, State *st, const Prior *pr,
                        double *partials, double *level1, double *hist, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_lm_pass<M, true>), dim3(sh.nchunk), dim3(kThreads), 0, s, sh, r, d, st, pr, partials);
-    hipLaunchKernelGGL(k_lm_reduce, dim3(kGroups), dim3(kRedThreads), 0, s, sh, st, 1, partials, level1);
+    hipLaunchKernelGGL((k_lm_pass<M, true, State>), dim3(sh.nchunk), dim3(kThreads), 0, s, sh, r, d, st, pr, partials);
+    hipLaunchKernelGGL(k_lm_reduce<State>, dim3(kGroups), dim3(kRedThreads), 0, s, sh, st, 1, partials, level1);
     hipLaunchKernelGGL((k_lm_global<M>), dim3(1), dim3(64), 0, s, sh, st, pr, 1, level1, hist);
     return hipGetLastError();
 }
@@ -585,7 +278,7 @@ template <int M>
 hipError_t launch_pass(const Shape &sh, const double *r, const double *d, State *st, const Prior *pr,
                        double *partials, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_lm_pass<M, false>), dim3(sh.nchunk), dim3(kThreads), 0, s, sh, r, d, st, pr, partials);
+    hipLaunchKernelGGL((k_lm_pass<M, false, State>), dim3(sh.nchunk), dim3(kThreads), 0, s, sh, r, d, st, pr, partials);
     return hipGetLastError();
 }
 
@@ -637,44 +330,6 @@ hipError_t genes_M(int M, const Shape &sh, const double *r, const double *d, con
 #undef CALL
 }
 
-// Host Cholesky of an SPD matrix: inverse and ln det; false if not SPD.
-bool host_spd_inverse(int M, const double *A, double *Ainv, double *lndet)
-{
-    std::vector<double> L(M * M, 0.0), Li(M * M, 0.0);
-    double ld = 0.0;
-    for (int j = 0; j < M; ++j) {
-        double s = A[j * M + j];
-        for (int k = 0; k < j; ++k) s -= L[j * M + k] * L[j * M + k];
-        if (!(s > 0.0) || !isfinite(s)) return false;
-        const double ljj = sqrt(s);
-        ld += 2.0 * log(ljj);
-        L[j * M + j] = ljj;
-        for (int i = j + 1; i < M; ++i) {
-            double t = A[i * M + j];
-            if (fabs(A[i * M + j] - A[j * M + i]) > 1e-12 * (fabs(A[i * M + j]) + fabs(A[j * M + i])) + 1e-300)
-                return false;  // not symmetric
-            for (int k = 0; k < j; ++k) t -= L[i * M + k] * L[j * M + k];
-            L[i * M + j] = t / ljj;
-        }
-    }
-    for (int j = 0; j < M; ++j) {
-        Li[j * M + j] = 1.0 / L[j * M + j];
-        for (int i = j + 1; i < M; ++i) {
-            double s = 0.0;
-            for (int k = j; k < i; ++k) s -= L[i * M + k] * Li[k * M + j];
-            Li[i * M + j] = s / L[i * M + i];
-        }
-    }
-    for (int i = 0; i < M; ++i)
-        for (int j = 0; j < M; ++j) {
-            double s = 0.0;
-            for (int k = (i > j ? i : j); k < M; ++k) s += Li[k * M + i] * Li[k * M + j];
-            Ainv[i * M + j] = s;
-        }
-    if (lndet) *lndet = ld;
-    return true;
-}
-
 }  // namespace
 
 struct lmvb_ctx {
@@ -714,14 +369,7 @@ cavi_status lmvb_create(lmvb_ctx **out, const double *r_dev, const double *d_dev
         p.q0 = 0.001;
         p.n0 = 1.0;
         for (int i = 0; i < M; ++i) p.K0[i] = 1.0 / N;
-        if (M == 2) {
-            // L0 = [[0.01, 0.005], [0.005, 0.008]]^-1
-            const double A[4] = {0.01, 0.005, 0.005, 0.008};
-            host_spd_inverse(2, A, p.L0, nullptr);
-        } else {
-            for (int i = 0; i < M; ++i)
-                for (int j = 0; j < M; ++j) p.L0[i * M + j] = i == j ? 100.0 : 0.0;
-        }
+        paper_L0(M, p.L0);
     }
     for (double v : {p.a0, p.b0, p.q0, p.n0})
         if (!(v > 0.0) || !isfinite(v)) return lfail(CAVI_E_INVAL, "prior a0, b0, q0, n0 must be finite and > 0");
@@ -737,13 +385,7 @@ cavi_status lmvb_create(lmvb_ctx **out, const double *r_dev, const double *d_dev
     }
     p.lg_a0 = lgamma(p.a0);
     lmvb_ctx *h = new lmvb_ctx;
-    h->sh.V = V;
-    h->sh.N = N;
-    h->sh.M = M;
-    h->sh.ppt = (int32_t)std::min<int64_t>(kPerThreadMax, std::max<int64_t>(1, (V + (1 << 18) - 1) >> 18));
-    const int64_t chunk = (int64_t)kThreads * h->sh.ppt;
-    h->sh.nchunk = (int32_t)((V + chunk - 1) / chunk);
-    h->sh.S = M + M * (M + 1) / 2 + 2;
+    h->sh = make_shape(V, N);
     h->r = r_dev;
     h->d = d_dev;
     hipError_t e = hipSuccess;

@@ -144,3 +144,40 @@ def test_lmvb_symbols_exported_and_argument_checks(L):
     assert LL.lmvb_init(None) == cavi.CAVI_E_INVAL
     assert LL.lmvb_sweep(None, 1, None) == cavi.CAVI_E_INVAL
     assert LL.lmvb_destroy(None) == cavi.CAVI_OK
+
+
+def test_lmem_symbols_exported_and_argument_checks(L):
+    """include/lmem.h: every declared entry point is exported; shape, pointer, alignment and start
+    checks return CAVI_E_INVAL before any device call."""
+    import numpy as np
+
+    from paper_2401_10068_amd import lmem
+
+    text = open(os.path.join(ROOT, "include", "lmem.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = sorted(set(re.findall(r"\b(lmem_[a-z0-9_]+)\s*\(", text)))
+    assert len(names) == 7, names
+    LL = lmem.lib()
+    for n in names:
+        assert hasattr(LL, n), n
+
+    def create(r, d, V, N, start=None):
+        h = C.c_void_p()
+        return LL.lmem_create(C.byref(h), C.c_void_p(r), C.c_void_p(d), V, N, C.byref(start) if start else None, None)
+
+    ok = 1 << 20  # any aligned non-NULL address: the checks below fail before it is used
+    for r, d, V, N in [(0, ok, 10, 3), (ok, 0, 10, 3), (ok + 4, ok, 10, 3), (ok, ok + 1, 10, 3), (ok, ok, 0, 3),
+                       (ok, ok, 10, 1), (ok, ok, 10, 9), (ok, ok, 1 << 40, 3)]:
+        assert create(r, d, V, N) == cavi.CAVI_E_INVAL, (r, d, V, N)
+    K = np.array([0.3, 0.3])
+    for rho, Lam in [(1.0, np.array([[1.0, 2.0], [2.0, 1.0]])), (1.0, np.array([[2.0, 0.5], [0.1, 2.0]])),
+                     (0.0, np.eye(2)), (float("inf"), np.eye(2)), (float("nan"), np.eye(2))]:
+        st = lmem.lmem_start(rho, cavi._dp(K), cavi._dp(np.ascontiguousarray(Lam)))
+        assert create(ok, ok, 10, 3, st) == cavi.CAVI_E_INVAL, (rho, Lam)
+    Kn = np.array([0.3, float("nan")])
+    st = lmem.lmem_start(1.0, cavi._dp(Kn), cavi._dp(np.eye(2)))
+    assert create(ok, ok, 10, 3, st) == cavi.CAVI_E_INVAL
+    assert LL.lmem_iterate(None, 1, None) == cavi.CAVI_E_INVAL
+    assert LL.lmem_run(None, 1, 0.0, None, None) == cavi.CAVI_E_INVAL
+    assert LL.lmem_get_params(None, None, None, None, None) == cavi.CAVI_E_INVAL
+    assert LL.lmem_destroy(None) == cavi.CAVI_OK

@@ -1,0 +1,176 @@
+"""GPU path of the paper's EM for its linear-mixing model vs its FP64 oracle, through the C ABI.
+
+Both sides are FP64 and take the same steps (Section 4.2, eqs 42-47); they differ in the order of
+the sums over genes, in the small matrix factorisations (Cholesky or closed form on the GPU, LU in
+numpy) and in how the log-likelihood is formed (from the E-step's sums on the GPU, gene by gene in
+the oracle).  Bars: estimates, the E-step of every gene and the log-likelihoods within 1e-9 of each
+array's largest magnitude after 1 and 3 iterations and after a run to convergence; bitwise run to
+run.  Cases: V = 1 (the smallest), ragged chunks, N = 2 (scalar weights) to N = 8 (the largest), the
+paper's N = 3 at its V = 8000, and V = 10^7 (the bench size).
+"""
+import numpy as np
+import pytest
+
+from oracle import lmem_oracle as le
+from oracle import lmvb_oracle as lo
+from paper_2401_10068_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2401_10068_amd import lmem
+
+    lmem.lib()  # fail loudly if the library is missing
+    return torch
+
+
+def gen(V, N, seed=1):
+    M = N - 1
+    rng = np.random.default_rng(seed)
+    K = rng.dirichlet(np.ones(N))[:M]
+    return synth.linmix_dataset(seed, V, K)
+
+
+def rel(g, o):
+    """max |g - o| over the array relative to max |o| (normwise)."""
+    g, o = np.asarray(g, dtype=np.float64), np.asarray(o, dtype=np.float64)
+    return float(np.max(np.abs(g - o)) / max(np.max(np.abs(o)), 1e-300))
+
+
+def check(h, p, r, d, what, genes=True):
+    g = h.params()
+    for name, got, ref in (("rho", g["rho"], p.rho), ("K", g["K"], p.K), ("Lam", g["Lam"], p.Lam),
+                           ("Laminv", g["Laminv"], np.linalg.inv(p.Lam))):
+        e = rel(got, ref)
+        assert e <= RTOL, f"{what} {name}: {e:.2e}"
+    if genes:
+        Sig, Mi, _ = le.e_step(r, d, p)
+        gM, gS = h.genes()
+        eM, eS = rel(gM.cpu().numpy(), Mi), rel(gS.cpu().numpy(), Sig)
+        assert eM <= RTOL and eS <= RTOL, f"{what} E-step: M {eM:.2e} Sigma {eS:.2e}"
+
+
+@pytest.mark.parametrize("V,N", [(1, 3), (7, 2), (8192 + 5, 3), (3 * 8192 - 1, 5), (500, 8), (8000, 3)])
+def test_iterations_match_oracle(torch_cuda, V, N):
+    from paper_2401_10068_amd.lmem import LinMixEM
+
+    torch = torch_cuda
+    r, d = gen(V, N)
+    h = LinMixEM(torch.from_numpy(r).cuda(), torch.from_numpy(d).cuda())
+    p = le.start(N)
+    check(h, p, r, d, "start")
+    done = 0
+    for n in (1, 2):
+        lg = h.iterate(n)
+        lo_ = []
+        for _ in range(n):
+            lo_.append(le.loglik(r, d, p))
+            p = le.iterate(r, d, p)
+        done += n
+        assert rel(lg, lo_) <= RTOL, f"log-likelihood after {done}: {rel(lg, lo_):.2e}"
+        check(h, p, r, d, f"after {done}")
+    h.close()
+
+
+def test_start_given(torch_cuda):
+    from paper_2401_10068_amd.lmem import LinMixEM
+
+    torch = torch_cuda
+    r, d = gen(3000, 4, seed=5)
+    A = np.array([[3.0, 0.5, 0.1], [0.5, 2.0, 0.2], [0.1, 0.2, 4.0]])
+    p = le.Params(20.0, np.array([0.2, 0.3, 0.1]), A)
+    h = LinMixEM(torch.from_numpy(r).cuda(), torch.from_numpy(d).cuda(), start=dict(rho=p.rho, K=p.K, Lam=p.Lam))
+    check(h, p, r, d, "start")
+    lg = h.iterate(3)
+    lo_ = []
+    for _ in range(3):
+        lo_.append(le.loglik(r, d, p))
+        p = le.iterate(r, d, p)
+    assert rel(lg, lo_) <= RTOL
+    check(h, p, r, d, "after 3")
+    h.close()
+
+
+def test_run_to_convergence_matches_oracle(torch_cuda):
+    from paper_2401_10068_amd.lmem import LinMixEM
+
+    torch = torch_cuda
+    r, d = synth.linmix_dataset(1, 8000, (0.1, 0.3))
+    h = LinMixEM(torch.from_numpy(r).cuda(), torch.from_numpy(d).cuda())
+    tol = 1e-7
+    n, ll, conv = h.run(max_iter=5000, rel_tol=tol)
+    assert conv and 2 <= n < 5000
+    p, hist = le.run(r, d, n)
+    assert rel(ll, hist[-1]) <= RTOL
+    # the oracle's own test of the same rule stops at the same iteration
+    rl = [abs(hist[t] - hist[t - 1]) <= tol * abs(hist[t]) for t in range(1, n)]
+    assert rl[-1] and not any(rl[:-1])
+    assert np.diff(hist).min() >= -1e-11 * abs(hist[-1])  # EM never lowers the likelihood
+    check(h, p, r, d, "converged")
+    assert np.linalg.norm(p.K - np.array([0.1, 0.3])) < 0.037  # as close as Table 1's estimates
+    h.close()
+
+
+def test_bitwise_run_to_run(torch_cuda):
+    from paper_2401_10068_amd.lmem import LinMixEM
+
+    torch = torch_cuda
+    r, d = gen(50000, 4, seed=3)
+    out = []
+    for _ in range(2):
+        h = LinMixEM(torch.from_numpy(r).cuda(), torch.from_numpy(d).cuda())
+        e = h.iterate(5)
+        g = h.params()
+        out.append((e.tobytes(), g["rho"], g["K"].tobytes(), g["Lam"].tobytes()))
+        h.close()
+    assert out[0] == out[1]
+
+
+def test_errors(torch_cuda):
+    from paper_2401_10068_amd import cavi
+    from paper_2401_10068_amd.lmem import LinMixEM
+
+    torch = torch_cuda
+    r, d = gen(100, 3)
+    r[5] = np.nan
+    h = LinMixEM(torch.from_numpy(r).cuda(), torch.from_numpy(d).cuda())
+    with pytest.raises(cavi.CaviError) as ei:
+        h.iterate(1)
+    assert ei.value.status == cavi.CAVI_E_NUMERIC
+    g = h.params()  # the estimates keep the start
+    assert g["rho"] == 1.0 and np.all(g["K"] == 1.0 / 3)
+    h.close()
+
+
+def test_full_size_two_iterations(torch_cuda):
+    """V = 10^7 genes, N = 3 (the bench size): every gene's E-step and the estimates after two
+    iterations."""
+    from paper_2401_10068_amd.lmem import LinMixEM
+
+    torch = torch_cuda
+    V = 10_000_000
+    r, d = synth.linmix_dataset(2, V, (0.1, 0.3))
+    h = LinMixEM(torch.from_numpy(r).cuda(), torch.from_numpy(d).cuda())
+    lg = h.iterate(2)
+    p = le.start(3)
+    lo_, scale = [], []
+    for _ in range(2):
+        lo_.append(le.loglik(r, d, p))
+        Sig, Mi, S = le.e_step(r, d, p)
+        # the GPU forms the log-likelihood from terms of order V that cancel to the result: its
+        # FP64 rounding is of the order of the largest of them
+        _, ldP = np.linalg.slogdet(np.linalg.inv(Sig))
+        scale.append(0.5 * max(V * abs(np.log(p.rho)), p.rho * S.sum(), V * abs(np.linalg.slogdet(p.Lam)[1]),
+                               abs(ldP.sum())))
+        p = le.m_step(Sig, Mi, S)
+    for t in range(2):
+        assert abs(lg[t] - lo_[t]) <= RTOL * scale[t], (t, lg[t], lo_[t], scale[t])
+    check(h, p, r, d, "V=1e7", genes=True)
+    h.close()
