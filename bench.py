@@ -27,6 +27,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 LM_KERNEL = "k_lm_pass"  # the per-gene pass of the linear-mixing VB and EM
 LM_SRC = os.path.join(ROOT, "paper_2401_10068_amd", "csrc", "linmix.h")
+GIBBS_KERNEL = "k_gibbs_pass"
+GIBBS_SRC = os.path.join(ROOT, "paper_2401_10068_amd", "csrc", "gibbs.hip")
 
 
 def kernel_sha(src: str = KERNEL_SRC) -> str:
@@ -295,6 +297,113 @@ def em_bench(args) -> int:
     return 0
 
 
+def gibbs_bench(args) -> int:
+    """The paper's Gibbs sampler for its linear-mixing model (Section 4.1, eqs 32-40) on the same
+    genes as the variational workload: V genes with N = 3 networks, K = (0.1, 0.3), rho = 100.  A
+    step is one iteration (every beta_i drawn from its full conditional, then rho, Lambda and K)."""
+    import numpy as np
+    import torch
+
+    from paper_2401_10068_amd import synth
+    from paper_2401_10068_amd.gibbs import LinMixGibbs
+
+    V, N, K_true, seed = 10_000_000, 3, (0.1, 0.3), 2
+    r, d = synth.linmix_dataset(seed, V, K_true)
+    rd, dd = torch.from_numpy(r).cuda(), torch.from_numpy(d).cuda()
+    torch.cuda.synchronize()
+    h = LinMixGibbs(rd, dd, seed=seed)
+    if args.warmup:
+        h.iterate(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.iterate(args.steps)
+    sec = time.perf_counter() - t0
+    pass_ms = h.profile_pass(20)
+    h.close()
+    bytes_per_pass = 8.0 * V * (N + 1)  # r and d read once, FP64
+    achieved = bytes_per_pass / (pass_ms * 1e-3) / 1e9
+    # the Gibbs column of Table 1: its five weight vectors, V = 8000 genes, the paper's 8000
+    # iterations (its chain converged in 8000); the posterior mean of K after 1000 discarded
+    table1 = []
+    TABLE1_GIBBS = [((0.1, 0.3), (0.1011, 0.3003)), ((0.13, 0.25), (0.1234, 0.2311)),
+                    ((0.39, 0.54), (0.3829, 0.5312)), ((0.25, 0.16), (0.2441, 0.1948)),
+                    ((0.18, 0.29), (0.1822, 0.2643))]
+    chain_s = 0.0
+    for row, (k_true, k_paper) in enumerate(TABLE1_GIBBS):
+        rs, ds = synth.linmix_dataset(1 + row, 8000, k_true)
+        hs = LinMixGibbs(torch.from_numpy(rs).cuda(), torch.from_numpy(ds).cuda(), seed=100 + row)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        hs.iterate(8000)
+        chain_s += time.perf_counter() - t1
+        _, Kc, _ = hs.chain(1000, 7000)
+        hs.close()
+        ke = Kc.mean(0)
+        table1.append({"actual": list(k_true), "gibbs": [round(float(v), 4) for v in ke],
+                       "error": float(np.linalg.norm(ke - np.array(k_true))), "paper_gibbs": list(k_paper)})
+    if args.copy_ref:
+        src = torch.ones(96_000_000, dtype=torch.float32, device=rd.device)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+    out = {
+        "metric": "Gibbs iterations/s of the paper's linear-mixing model (genes x iterations / s, %HBM peak)",
+        "value": V * args.steps / sec,
+        "unit": "genes*iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"linear-mixing Gibbs (Section 4.1), V={V} genes, N={N}, K={K_true}, rho=100, seed {seed}",
+                   "V": V, "N": N},
+        "roofline": {
+            "kernel": GIBBS_KERNEL,
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic("gibbs", GIBBS_SRC),
+            "avg_ms": pass_ms,
+            "bytes_per_launch": bytes_per_pass,
+        },
+        "table1": table1,
+        "table1_mean_error": sum(t["error"] for t in table1) / len(table1),
+        "table1_chain_seconds_per_8000_iterations_V8000": chain_s / len(table1),
+    }
+    if not args.no_cpu:
+        from oracle import gibbs_oracle as go
+        from oracle import lmvb_oracle as lo
+
+        Vs = 1_000_000
+        pr = lo.default_prior(N)
+        c = go.start(N, pr)
+        rng = go.Rng(seed)
+        iters = 0
+        t0 = time.perf_counter()
+        while True:
+            go.iterate(r[:Vs], d[:Vs], c, pr, rng)
+            iters += 1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_seconds:
+                break
+        out["cpu_baseline"] = {
+            "value": Vs * iters / el, "unit": "genes*iterations/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} iteration(s) on the first {Vs} genes of the same data from the start ({el:.1f} s, "
+                      f"numpy FP64, one thread)"}
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def batch_bench(args) -> int:
     """Time to ELBO convergence (1e-6 relative) of a batch of datasets: batched
     (one set of launches per sweep for all datasets) against plain GPU CAVI run
@@ -463,7 +572,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c2", choices=["small", "c2", "c3", "c4", "c5", "lm", "em"])
+    ap.add_argument("--workload", default="c2", choices=["small", "c2", "c3", "c4", "c5", "lm", "em", "gibbs"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
     ap.add_argument("--copy-ref", action="store_true",
@@ -490,6 +599,8 @@ def main() -> int:
         return lm_bench(args)
     if args.workload == "em":
         return em_bench(args)
+    if args.workload == "gibbs":
+        return gibbs_bench(args)
     import torch
 
     from paper_2401_10068_amd import synth

@@ -125,7 +125,8 @@ class Rng:
             _, _, x, _ = self._global_block(stream, t, 2 * k)
             u, _, _, _ = self._global_block(stream, t, 2 * k + 1)
             x, u = float(x), float(u)
-            v = (1.0 + c * x) ** 3
+            w = 1.0 + c * x
+            v = w * w * w
             if v > 0.0 and math.log(u) < 0.5 * x * x + d - d * v + d * math.log(v):
                 return d * v / rate
             k += 1

@@ -16,6 +16,7 @@
 #include "cavi_impl.h"
 #include "devmath.h"
 #include "../../include/cavi.h"
+#include "../../include/lmvb.h"
 
 namespace {
 
@@ -400,6 +401,34 @@ void paper_L0(int M, double *L0)
     }
     for (int i = 0; i < M; ++i)
         for (int j = 0; j < M; ++j) L0[i * M + j] = i == j ? 100.0 : 0.0;
+}
+
+// The prior constants of eqs 5-7 from the caller's (NULL: the paper's, Section 3.5: a0 = b0 = 0.5,
+// q0 = 0.001, n0 = 1, K0 = 1/N, L0 as paper_L0), with L0^-1 and ln det L0.  Returns NULL, or the
+// reason the constants are invalid.
+const char *fill_prior(const lmvb_prior *in, int M, Prior &p, double *lndetL0)
+{
+    if (in) {
+        p.a0 = in->a0;
+        p.b0 = in->b0;
+        p.q0 = in->q0;
+        p.n0 = in->n0;
+        if (!in->K0 || !in->L0) return "prior K0 or L0 is NULL";
+        for (int i = 0; i < M; ++i) p.K0[i] = in->K0[i];
+        for (int i = 0; i < M * M; ++i) p.L0[i] = in->L0[i];
+    } else {
+        p.a0 = p.b0 = 0.5;
+        p.q0 = 0.001;
+        p.n0 = 1.0;
+        for (int i = 0; i < M; ++i) p.K0[i] = 1.0 / (M + 1);
+        paper_L0(M, p.L0);
+    }
+    for (double v : {p.a0, p.b0, p.q0, p.n0})
+        if (!(v > 0.0) || !isfinite(v)) return "prior a0, b0, q0, n0 must be finite and > 0";
+    for (int i = 0; i < M; ++i)
+        if (!isfinite(p.K0[i])) return "prior K0 is not finite";
+    if (!host_spd_inverse(M, p.L0, p.L0inv, lndetL0)) return "prior L0 is not symmetric positive definite";
+    return nullptr;
 }
 
 }  // namespace

@@ -356,27 +356,8 @@ cavi_status lmvb_create(lmvb_ctx **out, const double *r_dev, const double *d_dev
     if (N < 2 || N > kMaxM + 1) return lfail(CAVI_E_INVAL, "N=%d outside [2, %d]", N, kMaxM + 1);
     const int M = N - 1;
     Prior p{};
-    if (prior) {
-        p.a0 = prior->a0;
-        p.b0 = prior->b0;
-        p.q0 = prior->q0;
-        p.n0 = prior->n0;
-        if (!prior->K0 || !prior->L0) return lfail(CAVI_E_INVAL, "prior K0 or L0 is NULL");
-        for (int i = 0; i < M; ++i) p.K0[i] = prior->K0[i];
-        for (int i = 0; i < M * M; ++i) p.L0[i] = prior->L0[i];
-    } else {
-        p.a0 = p.b0 = 0.5;
-        p.q0 = 0.001;
-        p.n0 = 1.0;
-        for (int i = 0; i < M; ++i) p.K0[i] = 1.0 / N;
-        paper_L0(M, p.L0);
-    }
-    for (double v : {p.a0, p.b0, p.q0, p.n0})
-        if (!(v > 0.0) || !isfinite(v)) return lfail(CAVI_E_INVAL, "prior a0, b0, q0, n0 must be finite and > 0");
-    for (int i = 0; i < M; ++i)
-        if (!isfinite(p.K0[i])) return lfail(CAVI_E_INVAL, "prior K0[%d] is not finite", i);
     double lndetL0 = 0.0;
-    if (!host_spd_inverse(M, p.L0, p.L0inv, &lndetL0)) return lfail(CAVI_E_INVAL, "prior L0 is not symmetric positive definite");
+    if (const char *why = fill_prior(prior, M, p, &lndetL0)) return lfail(CAVI_E_INVAL, "%s", why);
     if (!(p.n0 + (double)V > M - 1)) return lfail(CAVI_E_INVAL, "n0 + V must exceed N - 2 (a proper posterior Wishart)");
     if (p.n0 > M - 1) {
         double s = 0.0;

@@ -181,3 +181,44 @@ def test_lmem_symbols_exported_and_argument_checks(L):
     assert LL.lmem_run(None, 1, 0.0, None, None) == cavi.CAVI_E_INVAL
     assert LL.lmem_get_params(None, None, None, None, None) == cavi.CAVI_E_INVAL
     assert LL.lmem_destroy(None) == cavi.CAVI_OK
+
+
+def test_gibbs_symbols_exported_and_argument_checks(L):
+    """include/gibbs.h: every declared entry point is exported; shape, pointer, alignment and prior
+    checks return CAVI_E_INVAL before any device call."""
+    import numpy as np
+
+    from paper_2401_10068_amd import gibbs, lmvb
+
+    text = open(os.path.join(ROOT, "include", "gibbs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = sorted(set(re.findall(r"\b(gibbs_[a-z0-9_]+)\s*\(", text)))
+    assert len(names) == 7, names
+    LL = gibbs.lib()
+    for n in names:
+        assert hasattr(LL, n), n
+
+    def create(r, d, V, N, prior=None):
+        h = C.c_void_p()
+        return LL.gibbs_create(C.byref(h), C.c_void_p(r), C.c_void_p(d), V, N, C.byref(prior) if prior else None, 1,
+                               None)
+
+    ok = 1 << 20  # any aligned non-NULL address: the checks below fail before it is used
+    for r, d, V, N in [(0, ok, 10, 3), (ok, 0, 10, 3), (ok + 4, ok, 10, 3), (ok, ok + 1, 10, 3), (ok, ok, 0, 3),
+                       (ok, ok, 10, 1), (ok, ok, 10, 9), (ok, ok, 1 << 40, 3)]:
+        assert create(r, d, V, N) == cavi.CAVI_E_INVAL, (r, d, V, N)
+    K0 = np.array([0.3, 0.3])
+    for a0, b0, q0, n0, L0 in [(0.5, 0.5, 0.001, 1.0, np.array([[1.0, 2.0], [2.0, 1.0]])),
+                               (-1.0, 0.5, 0.001, 1.0, np.eye(2)), (0.5, 0.5, float("nan"), 1.0, np.eye(2))]:
+        pr = lmvb.lmvb_prior(a0, b0, q0, n0, cavi._dp(K0), cavi._dp(np.ascontiguousarray(L0)))
+        assert create(ok, ok, 10, 3, pr) == cavi.CAVI_E_INVAL
+    # Gamma draws need shape >= 1: n0 + V >= N - 1 (V = 1, N = 8, n0 = 1 fails) and a0 + V/2 >= 1
+    K7 = np.full(7, 0.125)
+    pr = lmvb.lmvb_prior(0.5, 0.5, 0.001, 1.0, cavi._dp(K7), cavi._dp(np.eye(7)))
+    assert create(ok, ok, 1, 8, pr) == cavi.CAVI_E_INVAL
+    pr = lmvb.lmvb_prior(0.2, 0.5, 0.001, 1.0, cavi._dp(K0), cavi._dp(np.eye(2)))
+    assert create(ok, ok, 1, 3, pr) == cavi.CAVI_E_INVAL
+    assert LL.gibbs_iterate(None, 1) == cavi.CAVI_E_INVAL
+    assert LL.gibbs_get_chain(None, 0, 1, None, None, None) == cavi.CAVI_E_INVAL
+    assert LL.gibbs_get_genes(None, None) == cavi.CAVI_E_INVAL
+    assert LL.gibbs_destroy(None) == cavi.CAVI_OK

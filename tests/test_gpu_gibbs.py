@@ -1,0 +1,164 @@
+"""GPU path of the paper's Gibbs sampler vs its FP64 oracle, through the C ABI.
+
+Both sides draw the same counter-based random numbers (Philox4x32-10 with the same key and counters)
+and take the same steps (Section 4.1, eqs 32-40), so the chains agree draw for draw; they differ only
+in rounding (the order of the sums over genes, the small matrix factorisations, the device's FP64
+log, sin and cos).  Bars: every row of the chain, the state, and the last beta_i of every gene within
+1e-9 of each array's largest magnitude after 1 and 10 iterations; bitwise run to run.  Cases: V = 1
+(the smallest), ragged chunks, N = 2 (scalar weights) to N = 8 (the largest), the paper's N = 3 at
+its V = 8000, and V = 10^7 (the bench size).
+"""
+import numpy as np
+import pytest
+
+from oracle import gibbs_oracle as go
+from oracle import lmvb_oracle as lo
+from paper_2401_10068_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2401_10068_amd import gibbs
+
+    gibbs.lib()  # fail loudly if the library is missing
+    return torch
+
+
+def gen(V, N, seed=1):
+    M = N - 1
+    rng = np.random.default_rng(seed)
+    K = rng.dirichlet(np.ones(N))[:M]
+    return synth.linmix_dataset(seed, V, K)
+
+
+def rel(g, o):
+    g, o = np.asarray(g, dtype=np.float64), np.asarray(o, dtype=np.float64)
+    return float(np.max(np.abs(g - o)) / max(np.max(np.abs(o)), 1e-300))
+
+
+def compare(h, c, rows, r, d, what, genes=True):
+    n = len(rows[0])
+    rho, K, Lam = h.chain(0, n)
+    for name, got, ref in (("rho", rho, rows[0]), ("K", K, rows[1]), ("Lam", Lam, rows[2])):
+        for t in range(n):
+            e = rel(got[t], ref[t])
+            assert e <= RTOL, f"{what} row {t + 1} {name}: {e:.2e}"
+    s = h.state()
+    assert s["t"] == c.t
+    for name, ref in (("rho", c.rho), ("K", c.K), ("Lam", c.Lam)):
+        e = rel(s[name], ref)
+        assert e <= RTOL, f"{what} state {name}: {e:.2e}"
+    if genes:
+        e = rel(h.genes().cpu().numpy(), c.beta)
+        assert e <= RTOL, f"{what} beta: {e:.2e}"
+
+
+def oracle_rows(r, d, c, pr, rng, n, rows):
+    for _ in range(n):
+        a, b, L = go.iterate(r, d, c, pr, rng)
+        rows[0].append(a)
+        rows[1].append(b.copy())
+        rows[2].append(L.copy())
+
+
+@pytest.mark.parametrize("V,N", [(1, 3), (7, 2), (8192 + 5, 3), (3 * 8192 - 1, 5), (500, 8), (8000, 3)])
+def test_chain_matches_oracle(torch_cuda, V, N):
+    from paper_2401_10068_amd.gibbs import LinMixGibbs
+
+    torch = torch_cuda
+    r, d = gen(V, N)
+    seed = 40 + V
+    h = LinMixGibbs(torch.from_numpy(r).cuda(), torch.from_numpy(d).cuda(), seed=seed)
+    pr = lo.default_prior(N)
+    c = go.start(N, pr)
+    rng = go.Rng(seed)
+    rows = ([], [], [])
+    for n in (1, 9):
+        h.iterate(n)
+        oracle_rows(r, d, c, pr, rng, n, rows)
+        compare(h, c, rows, r, d, f"V={V} N={N} after {c.t}")
+    h.close()
+
+
+def test_given_prior(torch_cuda):
+    from paper_2401_10068_amd.gibbs import LinMixGibbs
+
+    torch = torch_cuda
+    r, d = gen(3000, 4, seed=5)
+    pr = lo.Prior(1.5, 0.2, 0.3, 5.0, np.array([0.2, 0.3, 0.1]),
+                  np.array([[30.0, 5.0, 1.0], [5.0, 20.0, 2.0], [1.0, 2.0, 40.0]]))
+    h = LinMixGibbs(torch.from_numpy(r).cuda(), torch.from_numpy(d).cuda(), seed=3,
+                    prior=dict(a0=pr.a0, b0=pr.b0, q0=pr.q0, n0=pr.n0, K0=pr.K0, L0=pr.L0))
+    c = go.start(4, pr)
+    rows = ([], [], [])
+    h.iterate(5)
+    oracle_rows(r, d, c, pr, go.Rng(3), 5, rows)
+    compare(h, c, rows, r, d, "given prior")
+    h.close()
+
+
+def test_bitwise_run_to_run_and_seeds(torch_cuda):
+    from paper_2401_10068_amd.gibbs import LinMixGibbs
+
+    torch = torch_cuda
+    r, d = gen(50000, 4, seed=3)
+    out = []
+    for seed in (7, 7, 8):
+        h = LinMixGibbs(torch.from_numpy(r).cuda(), torch.from_numpy(d).cuda(), seed=seed)
+        h.iterate(5)
+        rho, K, Lam = h.chain(0, 5)
+        out.append((rho.tobytes(), K.tobytes(), Lam.tobytes(), h.genes().cpu().numpy().tobytes()))
+        h.close()
+    assert out[0] == out[1]
+    assert out[0][0] != out[2][0]
+
+
+def test_chain_rows_and_errors(torch_cuda):
+    from paper_2401_10068_amd import cavi
+    from paper_2401_10068_amd.gibbs import LinMixGibbs
+
+    torch = torch_cuda
+    r, d = gen(100, 3)
+    h = LinMixGibbs(torch.from_numpy(r).cuda(), torch.from_numpy(d).cuda(), seed=1)
+    with pytest.raises(cavi.CaviError) as ei:
+        h.genes()
+    assert ei.value.status == cavi.CAVI_E_STATE
+    h.iterate(3)
+    with pytest.raises(cavi.CaviError):
+        h.chain(2, 2)  # row 4 not drawn yet
+    rho, K, _ = h.chain(1, 2)
+    rho_all, K_all, _ = h.chain(0, 3)
+    assert np.array_equal(rho, rho_all[1:]) and np.array_equal(K, K_all[1:])
+    assert np.all(K_all[0] == 1.0 / 3)  # row 1 holds the start K_1 = K0
+    h.close()
+    r[5] = np.nan
+    h = LinMixGibbs(torch.from_numpy(r).cuda(), torch.from_numpy(d).cuda(), seed=1)
+    with pytest.raises(cavi.CaviError) as ei:
+        h.iterate(1)
+    assert ei.value.status == cavi.CAVI_E_NUMERIC
+    assert h.state()["t"] == 0
+    h.close()
+
+
+def test_full_size_two_iterations(torch_cuda):
+    """V = 10^7 genes, N = 3 (the bench size): the chain and every gene's beta after two iterations."""
+    from paper_2401_10068_amd.gibbs import LinMixGibbs
+
+    torch = torch_cuda
+    V = 10_000_000
+    r, d = synth.linmix_dataset(2, V, (0.1, 0.3))
+    h = LinMixGibbs(torch.from_numpy(r).cuda(), torch.from_numpy(d).cuda(), seed=2)
+    h.iterate(2)
+    pr = lo.default_prior(3)
+    c = go.start(3, pr)
+    rows = ([], [], [])
+    oracle_rows(r, d, c, pr, go.Rng(2), 2, rows)
+    compare(h, c, rows, r, d, "V=1e7")
+    h.close()
