@@ -32,7 +32,6 @@ constexpr uint32_t kKey1 = 0x47494253u;
 constexpr uint32_t kGlobalTag = 0x80000000u;
 constexpr uint32_t kStreamRho = 1, kStreamK = 2, kStreamAOff = 3, kStreamChi = 16;
 constexpr double kTwoM53 = 1.1102230246251565404236316680908203125e-16;  // 2^-53
-constexpr double kTwoPi = 6.283185307179586231995926937088370323181152343750;
 constexpr int kMaxAttempts = 4096;  // Marsaglia-Tsang accepts with probability > 0.95 for shape >= 1
 constexpr int kChainCap = 1 << 16;
 
@@ -75,9 +74,12 @@ __device__ __forceinline__ Block draws(const W4 &w)
     b.u1 = u53(w.w0, w.w1);
     b.u2 = u53(w.w2, w.w3);
     const double R = sqrt(-2.0 * log(b.u1));
-    const double a = kTwoPi * b.u2;
-    b.zc = R * cos(a);
-    b.zs = R * sin(a);
+    // sin and cos of 2 pi u2 as sinpi and cospi of 2 u2: the same values to within rounding, with
+    // an exact argument reduction instead of the general one
+    double sn, cs;
+    sincospi(2.0 * b.u2, &sn, &cs);
+    b.zc = R * cs;
+    b.zs = R * sn;
     return b;
 }
 
@@ -146,8 +148,6 @@ template <int M>
 __device__ __forceinline__ void draw_beta(const double (&D)[M], double e, const Coef &c, uint32_t key0, uint32_t t,
                                           int64_t g, double (&beta)[M])
 {
-    double m[M], S[M][M], detP;
-    gene_factor<M>(D, e, c, m, S, detP);
     double z[M];
 #pragma unroll
     for (int j = 0; j < (M + 1) / 2; ++j) {
@@ -155,6 +155,30 @@ __device__ __forceinline__ void draw_beta(const double (&D)[M], double e, const 
         z[2 * j] = b.zc;
         if (2 * j + 1 < M) z[2 * j + 1] = b.zs;
     }
+    if constexpr (M == 1) {
+        // S = 1/p, C = 1/sqrt(p)
+        const double p = c.ELam[0] + c.Erho * D[0] * D[0];
+        const double q = rsqrt(p);
+        beta[0] = (c.ELamK[0] + c.Erho * D[0] * e) * (q * q) + q * z[0];
+        return;
+    }
+    if constexpr (M == 2) {
+        // P = [[p00, p01], [p01, p11]], S = P^-1 = [[p11, -p01], [-p01, p00]] / det; the Cholesky
+        // factor of S is C11 = 1/sqrt(p11), C00 = p11 C11 / sqrt(det), C10 = -p01 C11 / sqrt(det)
+        const double p00 = c.ELam[0] + c.Erho * D[0] * D[0];
+        const double p01 = c.ELam[1] + c.Erho * D[0] * D[1];
+        const double p11 = c.ELam[3] + c.Erho * D[1] * D[1];
+        const double sd = rsqrt(fma(p00, p11, -p01 * p01));
+        const double q = rsqrt(p11);
+        const double id = sd * sd;
+        const double b0 = c.ELamK[0] + c.Erho * D[0] * e, b1 = c.ELamK[1] + c.Erho * D[1] * e;
+        const double qs = q * sd;
+        beta[0] = (p11 * b0 - p01 * b1) * id + (p11 * qs) * z[0];
+        beta[1] = (p00 * b1 - p01 * b0) * id - (p01 * qs) * z[0] + q * z[1];
+        return;
+    }
+    double m[M], S[M][M], detP;
+    gene_factor<M>(D, e, c, m, S, detP);
     // Cholesky factor of the covariance S, in registers
     double L[M][M];
 #pragma unroll
