@@ -101,8 +101,10 @@ __device__ double gamma_draw(uint32_t key0, uint32_t stream, uint32_t t, double 
 {
     const double d = shape - 1.0 / 3.0, c = 1.0 / sqrt(9.0 * d);
     for (int k = 0; k < kMaxAttempts; ++k) {
-        const double x = global_block(key0, stream, t, 2u * k).zc;
-        const double u = global_block(key0, stream, t, 2u * k + 1u).u1;
+        const W4 wx = philox(2u * k, 0u, t, kGlobalTag + stream, key0, kKey1);
+        const W4 wu = philox(2u * k + 1u, 0u, t, kGlobalTag + stream, key0, kKey1);
+        const double x = sqrt(-2.0 * log(u53(wx.w0, wx.w1))) * cospi(2.0 * u53(wx.w2, wx.w3));
+        const double u = u53(wu.w0, wu.w1);
         const double w = 1.0 + c * x;
         const double v = w * w * w;
         if (v > 0.0 && log(u) < 0.5 * x * x + d - d * v + d * log(v)) return d * v / rate;
@@ -280,12 +282,31 @@ __global__ __launch_bounds__(64) void k_gibbs_global(Shape sh, GibbsState *st, c
         tot[lane] = v;
     }
     __syncthreads();
-    if (lane != 0) return;
+    // the draws of this step, each on a lane of its own (independent streams): lane 0 rho_t, lanes
+    // 1..M the chi-square variates of Bartlett's diagonal, lanes 32.. its below-diagonal normals,
+    // lanes 56.. the normals of K_{t+1}; a failed Gamma draw is recorded as -1
+    constexpr int NOFF = M * (M - 1) / 2, kLaneOff = 32, kLaneK = 56;
+    static_assert(M + 1 <= kLaneOff && kLaneOff + NOFF <= kLaneK && kLaneK + M <= 64, "draw lanes overlap");
+    __shared__ double gam[kMaxM + 1], zoff[kMaxM * (kMaxM - 1) / 2 + 1], zK[kMaxM];
     const double V = (double)sh.V;
     const uint32_t key0 = st->key0, t = st->t + 1;
-    bool ok = true;
+    const double n = pr->n0 + V + 1.0;
+    if (lane <= M) {
+        bool gok = true;
+        const double g = lane == 0 ? gamma_draw(key0, kStreamRho, t, pr->a0 + 0.5 * V, pr->b0 + 0.5 * tot[S - 1], gok)
+                                   : gamma_draw(key0, kStreamChi + (lane - 1), t + 1, 0.5 * (n - (lane - 1)), 0.5, gok);
+        gam[lane] = gok ? g : -1.0;
+    } else if (lane >= kLaneOff && lane < kLaneOff + NOFF) {
+        zoff[lane - kLaneOff] = global_normal(key0, kStreamAOff, t + 1, lane - kLaneOff);
+    } else if (lane >= kLaneK && lane < kLaneK + M) {
+        zK[lane - kLaneK] = global_normal(key0, kStreamK, t + 1, lane - kLaneK);
+    }
+    __syncthreads();
+    if (lane != 0) return;
+    bool ok = gam[0] > 0.0;
+    for (int i = 1; i <= M; ++i) ok = ok && gam[i] > 0.0;
     // rho_t (eqs 36, 37)
-    const double rho = gamma_draw(key0, kStreamRho, t, pr->a0 + 0.5 * V, pr->b0 + 0.5 * tot[S - 1], ok);
+    const double rho = gam[0];
     // Lambda_{t+1} (eqs 32-34) with K_t, by Bartlett's decomposition of Wishart(n, LamL^-1)
     double K[M], LamL[M * M], Sc[M * M], Lc[M * M], lnd;
     for (int i = 0; i < M; ++i) K[i] = st->K[i];
@@ -295,13 +316,12 @@ __global__ __launch_bounds__(64) void k_gibbs_global(Shape sh, GibbsState *st, c
             LamL[i * M + k] = pr->L0inv[i * M + k] + pr->q0 * (K[i] - pr->K0[i]) * (K[k] - pr->K0[k]) + tot[tri(M, a, b)];
         }
     ok = ok && spd_inverse<M>(LamL, Sc, lnd) && chol<M>(Sc, Lc);
-    const double n = pr->n0 + V + 1.0;
     double A[M * M];
     int q = 0;
     for (int i = 0; i < M; ++i) {
         for (int j = 0; j < M; ++j) A[i * M + j] = 0.0;
-        A[i * M + i] = sqrt(gamma_draw(key0, kStreamChi + i, t + 1, 0.5 * (n - i), 0.5, ok));
-        for (int j = 0; j < i; ++j) A[i * M + j] = global_normal(key0, kStreamAOff, t + 1, q++);
+        A[i * M + i] = sqrt(gam[1 + i]);
+        for (int j = 0; j < i; ++j) A[i * M + j] = zoff[q++];
     }
     double LA[M * M], Lam1[M * M];
     for (int i = 0; i < M; ++i)
@@ -322,7 +342,7 @@ __global__ __launch_bounds__(64) void k_gibbs_global(Shape sh, GibbsState *st, c
     ok = ok && spd_inverse<M>(P, Cv, lnd) && chol<M>(Cv, Ck);
     for (int i = 0; i < M; ++i) {
         double s = (pr->q0 * pr->K0[i] + tot[i]) / (pr->q0 + V);
-        for (int k = 0; k <= i; ++k) s += Ck[i * M + k] * global_normal(key0, kStreamK, t + 1, k);
+        for (int k = 0; k <= i; ++k) s += Ck[i * M + k] * zK[k];
         K1[i] = s;
     }
     ok = ok && isfinite(rho) && rho > 0.0;
