@@ -27,6 +27,7 @@ __device__ __forceinline__ double wave_sum(double v)
 struct MShared {
     double red[kMBlock / 64];
     double ak[kMaxK], psi_ak[kMaxK], lg_ak[kMaxK], term_k[kMaxK];
+    double psi_a[kMaxK], lg_a[kMaxK], ln_bt[kMaxK];  // per component: digamma, lgamma of a_kg; ln(beta_kg / 2 pi)
     double tmp[kMaxKG];
     double asum, psum, lg_asum, lg_prior;
     int bad;
@@ -191,7 +192,17 @@ __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, in
         sh.psi_ak[tid] = dev_digamma(a);
         sh.lg_ak[tid] = dev_lgamma(a);
         v.nalpha[tid] = a;
+    } else if (tid >= 64 && tid < 64 + K) {
+        // a_kg = a0 + N_k / 2 and beta_kg = beta0 + N_k are the same for every gene of a
+        // subpopulation: their special functions once per subpopulation, in other waves
+        const int k = tid - 64;
+        sh.psi_a[k] = dev_digamma(p.a0 + 0.5 * T0[k]);
+        sh.ln_bt[k] = log((p.beta0 + T0[k]) / kTwoPi);
+    } else if (tid >= 128 && tid < 128 + K) {
+        const int k = tid - 128;
+        sh.lg_a[k] = dev_lgamma(p.a0 + 0.5 * T0[k]);
     }
+    __syncthreads();
     const double half_ln_b0 = 0.5 * log(p.beta0 / kTwoPi);
     const double prior_const = half_ln_b0 + p.a0 * log(p.b0) - dev_lgamma(p.a0);
     double acc = 0.0;
@@ -217,7 +228,7 @@ __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, in
         nbt[it] = bt;
         nav[it] = aa;
         nbv[it] = bb;
-        const double elt = dev_digamma(aa) - log(bb);
+        const double elt = sh.psi_a[k] - log(bb);
         const double tb = aa / bb;
         if (!init_mode) {
             double sq = T2[q] - 2.0 * mp * T1[q] + Nk * mp * mp;  // sum r (x - m)^2
@@ -226,7 +237,7 @@ __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, in
             acc += 0.5 * (Nk * (elt - kLn2Pi) - tb * sq - Nk / bt);
             acc += prior_const + 0.5 * elt - 0.5 * p.beta0 * (tb * dm0 * dm0 + 1.0 / bt) + (p.a0 - 1.0) * elt
                    - p.b0 * tb;
-            acc -= 0.5 * log(bt / kTwoPi) + 0.5 * elt - 0.5 + aa * log(bb) - dev_lgamma(aa) + (aa - 1.0) * elt - aa;
+            acc -= 0.5 * sh.ln_bt[k] + 0.5 * elt - 0.5 + aa * log(bb) - sh.lg_a[k] + (aa - 1.0) * elt - aa;
         }
         sh.tmp[q] = coef_item(v, q, mm, bt, aa, bb, elt);
         if (!isfinite(mm) || !isfinite(bb) || !isfinite(elt) || !isfinite(T2[q])) bad = 1;
