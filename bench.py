@@ -426,6 +426,96 @@ def gibbs_bench(args) -> int:
     return 0
 
 
+def figs_bench(args) -> int:
+    """The paper's run-time experiment (Section 4, Figs 5-7): its linear-mixing model with N = 3 at
+    V = 4000, 5000, 6000, 7000 and 8000 genes, 4000 iterations of VB and of EM and 10,000 of the
+    Gibbs sampler, each timed from data already on the device to the last iteration's result on the
+    host.  The paper's GTX 1050 and i5-8300H times are printed beside them as context (another
+    machine): they are not a target.  At these sizes every kernel lasts a few microseconds, so the
+    runs are bound by launch latency, not by HBM or the ALUs."""
+    import torch
+
+    from paper_2401_10068_amd import synth
+    from paper_2401_10068_amd.gibbs import LinMixGibbs
+    from paper_2401_10068_amd.lmem import LinMixEM
+    from paper_2401_10068_amd.lmvb import LinMixVB
+
+    paper = {  # seconds: (VB GPU, VB CPU, EM GPU, EM CPU, Gibbs GPU, Gibbs CPU), Figs 5-7
+        4000: (62, 424, 53, 330, 201, 1202), 5000: (74, 522, 65, 405, 246, 1490),
+        6000: (88, 621, 78, 486, 297, 1785), 7000: (101, 723, 90, 560, 341, 2104),
+        8000: (116, 846, 104, 637, 389, 2391)}
+    runs = []
+    for V in sorted(paper):
+        r, d = synth.linmix_dataset(1, V, (0.1, 0.3))
+        rd, dd = torch.from_numpy(r).cuda(), torch.from_numpy(d).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = LinMixVB(rd, dd)
+        h.init()
+        h.sweep(4000)
+        h.globals()
+        vb = time.perf_counter() - t0
+        h.close()
+        t0 = time.perf_counter()
+        h = LinMixEM(rd, dd)
+        h.iterate(4000)
+        h.params()
+        em = time.perf_counter() - t0
+        h.close()
+        t0 = time.perf_counter()
+        h = LinMixGibbs(rd, dd, seed=1)
+        h.iterate(10000)
+        h.state()
+        gb = time.perf_counter() - t0
+        h.close()
+        pv = paper[V]
+        runs.append({"V": V, "vb_s": vb, "em_s": em, "gibbs_s": gb,
+                     "paper_gtx1050_s": {"vb": pv[0], "em": pv[2], "gibbs": pv[4]},
+                     "paper_i5_8300h_s": {"vb": pv[1], "em": pv[3], "gibbs": pv[5]}})
+    last = runs[-1]
+    out = {
+        "metric": "seconds for the paper's fixed-iteration runs (Figs 5-7): 4000 VB sweeps at V = 8000",
+        "value": last["vb_s"],
+        "unit": "s",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "linear-mixing model, N=3, K=(0.1, 0.3), rho=100, V=4000..8000 genes; VB and EM "
+                               "4000 iterations, Gibbs 10000"},
+        "runs": runs,
+        "roofline": None,
+        "note": "launch-latency bound: three kernels of a few microseconds per iteration",
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        from oracle import gibbs_oracle as go
+        from oracle import lmem_oracle as le
+        from oracle import lmvb_oracle as lo
+
+        r, d = synth.linmix_dataset(1, 8000, (0.1, 0.3))
+        pr = lo.default_prior(3)
+        n = 200
+        t0 = time.perf_counter()
+        lo.run(r, d, pr, n)
+        vb = (time.perf_counter() - t0) * 4000 / n
+        t0 = time.perf_counter()
+        le.run(r, d, n)
+        em = (time.perf_counter() - t0) * 4000 / n
+        t0 = time.perf_counter()
+        go.run(r, d, n, seed=1)
+        gb = (time.perf_counter() - t0) * 10000 / n
+        out["cpu_baseline"] = {
+            "value": vb, "unit": "s", "cores": 1, "kind": "oracle",
+            "em_s": em, "gibbs_s": gb,
+            "sample": f"{n} iterations of each oracle (VB with its bound, EM with its log-likelihood, Gibbs) at "
+                      f"V = 8000, scaled to 4000 / 4000 / 10000 iterations (numpy FP64, one thread)"}
+
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def batch_bench(args) -> int:
     """Time to ELBO convergence (1e-6 relative) of a batch of datasets: batched
     (one set of launches per sweep for all datasets) against plain GPU CAVI run
@@ -594,7 +684,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c2", choices=["small", "c2", "c3", "c4", "c5", "lm", "em", "gibbs"])
+    ap.add_argument("--workload", default="c2", choices=["small", "c2", "c3", "c4", "c5", "lm", "em", "gibbs", "figs"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
     ap.add_argument("--copy-ref", action="store_true",
@@ -623,6 +713,8 @@ def main() -> int:
         return em_bench(args)
     if args.workload == "gibbs":
         return gibbs_bench(args)
+    if args.workload == "figs":
+        return figs_bench(args)
     import torch
 
     from paper_2401_10068_amd import synth
