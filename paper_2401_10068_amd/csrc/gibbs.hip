@@ -406,7 +406,7 @@ hipError_t launch_giter(const Shape &sh, const double *r, const double *d, Gibbs
                         double *partials, double *level1, double *chain, hipStream_t s)
 {
     hipLaunchKernelGGL((k_gibbs_pass<M>), dim3(sh.nchunk), dim3(kThreads), 0, s, sh, r, d, st, partials);
-    hipLaunchKernelGGL(k_lm_reduce<GibbsState>, dim3(kGroups), dim3(kRedThreads), 0, s, sh, st, 0, partials, level1);
+    launch_lm_reduce(sh, st, 0, partials, level1, s);
     hipLaunchKernelGGL((k_gibbs_global<M>), dim3(1), dim3(64), 0, s, sh, st, pr, level1, chain);
     return hipGetLastError();
 }

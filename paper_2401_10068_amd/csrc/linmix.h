@@ -252,16 +252,15 @@ __global__ __launch_bounds__(kThreads) void k_lm_pass(Shape sh, const double *__
     }
 }
 
-// Group b sums chunks [b n / 16, (b + 1) n / 16): wave v a contiguous 1/16 of them in chunk order
-// (eight loads in flight), then the 16 waves in order.  Lane s holds sum s.
-template <class St>
-__global__ __launch_bounds__(kRedThreads) void k_lm_reduce(Shape sh, const St *st, int init_mode,
-                                                          const double *__restrict__ partials,
-                                                          double *__restrict__ level1)
+// Group b sums chunks [b n / 16, (b + 1) n / 16): wave v of the NT / 64 a contiguous share of them in
+// chunk order (eight loads in flight), then the waves in order.  Lane s holds sum s.
+template <class St, int NT>
+__global__ __launch_bounds__(NT) void k_lm_reduce(Shape sh, const St *st, int init_mode,
+                                                  const double *__restrict__ partials, double *__restrict__ level1)
 {
     if (!init_mode && skipped(st)) return;
-    __shared__ double part[kRedThreads / 64][64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = kRedThreads / 64;
+    __shared__ double part[NT / 64][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = NT / 64;
     const int b = blockIdx.x;
     const int c0 = (int)(((int64_t)sh.nchunk * b) / kGroups), c1 = (int)(((int64_t)sh.nchunk * (b + 1)) / kGroups);
     const int w0 = c0 + (int)(((int64_t)(c1 - c0) * wv) / nw), w1 = c0 + (int)(((int64_t)(c1 - c0) * (wv + 1)) / nw);
@@ -282,6 +281,21 @@ __global__ __launch_bounds__(kRedThreads) void k_lm_reduce(Shape sh, const St *s
         for (int w = 1; w < nw; ++w) t += part[w][lane];
         level1[(size_t)b * kMaxS + lane] = t;
     }
+}
+
+// Up to this many chunks (V <= 65536 genes) one wave sums each group: a 1024-thread workgroup costs
+// more to launch than such a group takes to add up.  The shape is a function of V only.
+constexpr int kSmallReduce = 256;
+
+template <class St>
+void launch_lm_reduce(const Shape &sh, const St *st, int init_mode, const double *partials, double *level1,
+                      hipStream_t s)
+{
+    if (sh.nchunk <= kSmallReduce)
+        hipLaunchKernelGGL((k_lm_reduce<St, 64>), dim3(kGroups), dim3(64), 0, s, sh, st, init_mode, partials, level1);
+    else
+        hipLaunchKernelGGL((k_lm_reduce<St, kRedThreads>), dim3(kGroups), dim3(kRedThreads), 0, s, sh, st, init_mode,
+                           partials, level1);
 }
 
 // Cholesky factor of an SPD M x M matrix (row-major), its inverse and ln det; false if not SPD.

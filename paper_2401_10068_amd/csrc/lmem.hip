@@ -163,7 +163,7 @@ hipError_t launch_iter(const Shape &sh, const double *r, const double *d, EmStat
 {
     hipLaunchKernelGGL((k_lm_pass<M, false, EmState>), dim3(sh.nchunk), dim3(kThreads), 0, s, sh, r, d, st,
                        (const Prior *)nullptr, partials);
-    hipLaunchKernelGGL(k_lm_reduce<EmState>, dim3(kGroups), dim3(kRedThreads), 0, s, sh, st, 0, partials, level1);
+    launch_lm_reduce(sh, st, 0, partials, level1, s);
     hipLaunchKernelGGL((k_em_global<M>), dim3(1), dim3(64), 0, s, sh, st, level1, hist);
     return hipGetLastError();
 }

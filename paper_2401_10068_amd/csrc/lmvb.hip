@@ -45,6 +45,18 @@ struct State {
     Coef used;  // the pass that formed the current q(beta)
 };
 
+// The M-sized part of a coefficient block, element by element (a whole-struct copy is held in
+// registers across the update and spills).
+template <int M>
+__device__ void copy_coef(Coef &dst, const Coef &src)
+{
+    dst.a_rho = src.a_rho;
+    dst.b_rho = src.b_rho;
+    dst.Erho = src.Erho;
+    for (int i = 0; i < M * M; ++i) dst.ELam[i] = src.ELam[i];
+    for (int i = 0; i < M; ++i) dst.ELamK[i] = src.ELamK[i];
+}
+
 // Coefficients of the next pass from q(rho) = Gamma(a, b) and q(K, Lambda) (eqs 28, 29, 31).
 template <int M>
 __device__ void next_coef(Coef &c, double a, double b, const double *W, const double *K0K, double nu)
@@ -75,7 +87,8 @@ __global__ __launch_bounds__(64) void k_lm_global(Shape sh, State *st, const Pri
     const int lane = threadIdx.x;
     const double V = (double)sh.V;
     const double nu = pr->n0 + V, kappa = pr->q0 + V;
-    const Coef used = st->coef;
+    // q(rho) of this sweep's pass (the coefficient block itself is copied to st->used at the end)
+    const double used_a = st->coef.a_rho, used_b = st->coef.b_rho;
     if (lane < S) {
         double t = level1[lane];
         for (int b = 1; b < kGroups; ++b) t += level1[(size_t)b * kMaxS + lane];
@@ -87,9 +100,9 @@ __global__ __launch_bounds__(64) void k_lm_global(Shape sh, State *st, const Pri
             sp[0][lane] = cavi::dev_digamma(x);
             sp[1][lane] = cavi::dev_lgamma(x);
         } else if (lane == M) {
-            sp[0][M] = cavi::dev_digamma(used.a_rho);
+            sp[0][M] = cavi::dev_digamma(used_a);
         } else if (lane == M + 1) {
-            sp[1][M] = cavi::dev_lgamma(used.a_rho);
+            sp[1][M] = cavi::dev_lgamma(used_a);
         }
     }
     __syncthreads();
@@ -132,7 +145,7 @@ __global__ __launch_bounds__(64) void k_lm_global(Shape sh, State *st, const Pri
     bool bad = !spd_inverse<M>(Winv, W, lndetWinv);
     const double lndetW = -lndetWinv;
     // the lower bound at q(rho) of this sweep, the new q(beta) and the new q(K, Lambda)
-    const double a = used.a_rho, b = used.b_rho;
+    const double a = used_a, b = used_b;
     const double Erho = a / b, Elnrho = sp[0][M] - log(b);
     double sdig = 0.0, slg = 0.0;
     for (int j = 0; j < M; ++j) {
@@ -179,7 +192,7 @@ __global__ __launch_bounds__(64) void k_lm_global(Shape sh, State *st, const Pri
     for (int i = 0; i < M * M; ++i) st->W[i] = W[i];
     st->nu = nu;
     st->kappa = kappa;
-    st->used = used;
+    copy_coef<M>(st->used, st->coef);
     st->swept = 1;
     next_coef<M>(st->coef, a1, b1, W, K0K, nu);
 }
@@ -234,7 +247,7 @@ hipError_t launch_sweep(const Shape &sh, const double *r, const double *d, State
                         double *partials, double *level1, double *hist, hipStream_t s)
 {
     hipLaunchKernelGGL((k_lm_pass<M, false, State>), dim3(sh.nchunk), dim3(kThreads), 0, s, sh, r, d, st, pr, partials);
-    hipLaunchKernelGGL(k_lm_reduce<State>, dim3(kGroups), dim3(kRedThreads), 0, s, sh, st, 0, partials, level1);
+    launch_lm_reduce(sh, st, 0, partials, level1, s);
     hipLaunchKernelGGL((k_lm_global<M>), dim3(1), dim3(64), 0, s, sh, st, pr, 0, level1, hist);
     return hipGetLastError();
 }
@@ -244,7 +257,7 @@ hipError_t launch_init(const Shape &sh, const double *r, const double *d, State 
                        double *partials, double *level1, double *hist, hipStream_t s)
 {
     hipLaunchKernelGGL((k_lm_pass<M, true, State>), dim3(sh.nchunk), dim3(kThreads), 0, s, sh, r, d, st, pr, partials);
-    hipLaunchKernelGGL(k_lm_reduce<State>, dim3(kGroups), dim3(kRedThreads), 0, s, sh, st, 1, partials, level1);
+    launch_lm_reduce(sh, st, 1, partials, level1, s);
     hipLaunchKernelGGL((k_lm_global<M>), dim3(1), dim3(64), 0, s, sh, st, pr, 1, level1, hist);
     return hipGetLastError();
 }
