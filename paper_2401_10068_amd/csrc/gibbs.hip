@@ -266,64 +266,84 @@ __global__ __launch_bounds__(kThreads) void k_gibbs_pass(Shape sh, const double 
     }
 }
 
-// One workgroup of 64 threads: lanes s < S add up sum s over the 16 groups in order; lane 0 draws
-// rho_t, then Lambda_{t+1} and K_{t+1}, and writes row t of the chain (rho_t, K_t, Lambda_t).
+// One workgroup of four waves, each on its own SIMD, so that independent work overlaps:
+//   wave 0: lanes s < S add up sum s over the 16 groups in order; lane 0 gathers them and forms the
+//           Cholesky factor of the Wishart scale Lambda_L^-1 (eqs 32-34 with K_t; no draw needed);
+//   wave 1: lanes 0..M-1 the chi-square variates of Bartlett's diagonal, lane M rho_t (its rate
+//           from the same group sums in the same order);
+//   wave 2: the below-diagonal normals of Bartlett's factor, then the normals of K_{t+1}.
+// Then wave 0's lane 0 forms Lambda_{t+1} and K_{t+1} and writes row t of the chain
+// (rho_t, K_t, Lambda_t).  A failed Gamma draw is recorded as -1.
 template <int M>
-__global__ __launch_bounds__(64) void k_gibbs_global(Shape sh, GibbsState *st, const Prior *pr,
-                                                     const double *__restrict__ level1, double *__restrict__ chain)
+__global__ __launch_bounds__(256) void k_gibbs_global(Shape sh, GibbsState *st, const Prior *pr,
+                                                      const double *__restrict__ level1, double *__restrict__ chain)
 {
     if (skipped(st)) return;
-    constexpr int S = M + M * (M + 1) / 2 + 1, R = 1 + M + M * M;
-    __shared__ double tot[kMaxS];
-    const int lane = threadIdx.x;
-    if (lane < S) {
-        double v = level1[lane];
-        for (int b = 1; b < kGroups; ++b) v += level1[(size_t)b * kMaxS + lane];
-        tot[lane] = v;
-    }
-    __syncthreads();
-    // the draws of this step, each on a lane of its own (independent streams): lane 0 rho_t, lanes
-    // 1..M the chi-square variates of Bartlett's diagonal, lanes 32.. its below-diagonal normals,
-    // lanes 56.. the normals of K_{t+1}; a failed Gamma draw is recorded as -1
-    constexpr int NOFF = M * (M - 1) / 2, kLaneOff = 32, kLaneK = 56;
-    static_assert(M + 1 <= kLaneOff && kLaneOff + NOFF <= kLaneK && kLaneK + M <= 64, "draw lanes overlap");
-    __shared__ double gam[kMaxM + 1], zoff[kMaxM * (kMaxM - 1) / 2 + 1], zK[kMaxM];
+    constexpr int S = M + M * (M + 1) / 2 + 1, R = 1 + M + M * M, NOFF = M * (M - 1) / 2;
+    static_assert(S <= 64 && M + 1 <= 64 && NOFF + M <= 64, "one wave per kind of work");
+    __shared__ double gam[kMaxM + 1], zn[kMaxM * (kMaxM - 1) / 2 + kMaxM];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const double V = (double)sh.V;
     const uint32_t key0 = st->key0, t = st->t + 1;
     const double n = pr->n0 + V + 1.0;
-    if (lane <= M) {
-        bool gok = true;
-        const double g = lane == 0 ? gamma_draw(key0, kStreamRho, t, pr->a0 + 0.5 * V, pr->b0 + 0.5 * tot[S - 1], gok)
-                                   : gamma_draw(key0, kStreamChi + (lane - 1), t + 1, 0.5 * (n - (lane - 1)), 0.5, gok);
-        gam[lane] = gok ? g : -1.0;
-    } else if (lane >= kLaneOff && lane < kLaneOff + NOFF) {
-        zoff[lane - kLaneOff] = global_normal(key0, kStreamAOff, t + 1, lane - kLaneOff);
-    } else if (lane >= kLaneK && lane < kLaneK + M) {
-        zK[lane - kLaneK] = global_normal(key0, kStreamK, t + 1, lane - kLaneK);
+    double tot[S], K[M], Lc[M * M];
+    bool ok = true;
+    if (wv == 0) {
+        double v = 0.0;
+        if (lane < S) {
+            v = level1[lane];
+            for (int b = 1; b < kGroups; ++b) v += level1[(size_t)b * kMaxS + lane];
+        }
+#pragma unroll
+        for (int q = 0; q < S; ++q) tot[q] = __shfl(v, q, 64);
+        if (lane == 0) {
+            // Lambda_L (eq 34) with K_t, and the Cholesky factor of its inverse
+            double LamL[M * M], Sc[M * M], lnd;
+            for (int i = 0; i < M; ++i) K[i] = st->K[i];
+            for (int i = 0; i < M; ++i)
+                for (int k = 0; k < M; ++k) {
+                    const int a = i < k ? i : k, b = i < k ? k : i;
+                    LamL[i * M + k] =
+                        pr->L0inv[i * M + k] + pr->q0 * (K[i] - pr->K0[i]) * (K[k] - pr->K0[k]) + tot[tri(M, a, b)];
+                }
+            ok = spd_inverse<M>(LamL, Sc, lnd) && chol<M>(Sc, Lc);
+        }
+    } else if (wv == 1) {
+        if (lane <= M) {
+            double shape = 0.5 * (n - lane), rate = 0.5;
+            uint32_t stream = kStreamChi + lane, tt = t + 1;
+            if (lane == M) {  // rho_t (eqs 36, 37)
+                double res = level1[S - 1];
+                for (int b = 1; b < kGroups; ++b) res += level1[(size_t)b * kMaxS + S - 1];
+                shape = pr->a0 + 0.5 * V;
+                rate = pr->b0 + 0.5 * res;
+                stream = kStreamRho;
+                tt = t;
+            }
+            bool gok = true;
+            const double g = gamma_draw(key0, stream, tt, shape, rate, gok);
+            gam[lane] = gok ? g : -1.0;
+        }
+    } else if (wv == 2) {
+        if (lane < NOFF + M) {
+            const bool off = lane < NOFF;
+            zn[lane] = global_normal(key0, off ? kStreamAOff : kStreamK, t + 1, off ? lane : lane - NOFF);
+        }
     }
     __syncthreads();
-    if (lane != 0) return;
-    bool ok = gam[0] > 0.0;
-    for (int i = 1; i <= M; ++i) ok = ok && gam[i] > 0.0;
-    // rho_t (eqs 36, 37)
-    const double rho = gam[0];
-    // Lambda_{t+1} (eqs 32-34) with K_t, by Bartlett's decomposition of Wishart(n, LamL^-1)
-    double K[M], LamL[M * M], Sc[M * M], Lc[M * M], lnd;
-    for (int i = 0; i < M; ++i) K[i] = st->K[i];
-    for (int i = 0; i < M; ++i)
-        for (int k = 0; k < M; ++k) {
-            const int a = i < k ? i : k, b = i < k ? k : i;
-            LamL[i * M + k] = pr->L0inv[i * M + k] + pr->q0 * (K[i] - pr->K0[i]) * (K[k] - pr->K0[k]) + tot[tri(M, a, b)];
-        }
-    ok = ok && spd_inverse<M>(LamL, Sc, lnd) && chol<M>(Sc, Lc);
+    if (threadIdx.x != 0) return;
+    const double rho = gam[M];
+    ok = ok && rho > 0.0;
+    for (int i = 0; i < M; ++i) ok = ok && gam[i] > 0.0;
+    // Lambda_{t+1} by Bartlett's decomposition of Wishart(n, LamL^-1)
     double A[M * M];
     int q = 0;
     for (int i = 0; i < M; ++i) {
         for (int j = 0; j < M; ++j) A[i * M + j] = 0.0;
-        A[i * M + i] = sqrt(gam[1 + i]);
-        for (int j = 0; j < i; ++j) A[i * M + j] = zoff[q++];
+        A[i * M + i] = sqrt(gam[i]);
+        for (int j = 0; j < i; ++j) A[i * M + j] = zn[q++];
     }
-    double LA[M * M], Lam1[M * M];
+    double LA[M * M], Lam1[M * M], lnd;
     for (int i = 0; i < M; ++i)
         for (int j = 0; j < M; ++j) {
             double s = 0.0;
@@ -342,7 +362,7 @@ __global__ __launch_bounds__(64) void k_gibbs_global(Shape sh, GibbsState *st, c
     ok = ok && spd_inverse<M>(P, Cv, lnd) && chol<M>(Cv, Ck);
     for (int i = 0; i < M; ++i) {
         double s = (pr->q0 * pr->K0[i] + tot[i]) / (pr->q0 + V);
-        for (int k = 0; k <= i; ++k) s += Ck[i * M + k] * zK[k];
+        for (int k = 0; k <= i; ++k) s += Ck[i * M + k] * zn[NOFF + k];
         K1[i] = s;
     }
     ok = ok && isfinite(rho) && rho > 0.0;
@@ -407,7 +427,7 @@ hipError_t launch_giter(const Shape &sh, const double *r, const double *d, Gibbs
 {
     hipLaunchKernelGGL((k_gibbs_pass<M>), dim3(sh.nchunk), dim3(kThreads), 0, s, sh, r, d, st, partials);
     launch_lm_reduce(sh, st, 0, partials, level1, s);
-    hipLaunchKernelGGL((k_gibbs_global<M>), dim3(1), dim3(64), 0, s, sh, st, pr, level1, chain);
+    hipLaunchKernelGGL((k_gibbs_global<M>), dim3(1), dim3(256), 0, s, sh, st, pr, level1, chain);
     return hipGetLastError();
 }
 

@@ -74,49 +74,80 @@ __device__ void next_coef(Coef &c, double a, double b, const double *W, const do
     }
 }
 
-// One workgroup of 64 threads.  Lanes j < M form digamma and lgamma of (nu + 1 - (j + 1)) / 2
-// (Wishart expectations), lanes M and M + 1 digamma and lgamma of a_rho; lane 0 does the rest.
+// One workgroup of three waves, each on its own SIMD, so that independent work overlaps:
+//   wave 0: lanes s < S add up sum s over the 16 groups in order; lane 0 gathers them and forms
+//           q(K, Lambda) (eqs 24, 25) and the parts of the bound that need no special function;
+//   wave 1: digamma of (nu + 1 - j) / 2 on lanes j - 1 < M (Wishart expectations) and of a_rho on
+//           lane M;
+//   wave 2: lgamma of the same arguments.
+// Then wave 0's lane 0 finishes the bound, the convergence test and q(rho).
 template <int M>
-__global__ __launch_bounds__(64) void k_lm_global(Shape sh, State *st, const Prior *pr, int init_mode,
-                                                  const double *__restrict__ level1, double *__restrict__ hist)
+__global__ __launch_bounds__(192) void k_lm_global(Shape sh, State *st, const Prior *pr, int init_mode,
+                                                   const double *__restrict__ level1, double *__restrict__ hist)
 {
     if (!init_mode && skipped(st)) return;
     constexpr int S = M + M * (M + 1) / 2 + 2;
-    __shared__ double tot[kMaxS];
+    static_assert(S <= 64, "one wave for the sums");
     __shared__ double sp[2][kMaxM + 2];
-    const int lane = threadIdx.x;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const double V = (double)sh.V;
     const double nu = pr->n0 + V, kappa = pr->q0 + V;
     // q(rho) of this sweep's pass (the coefficient block itself is copied to st->used at the end)
     const double used_a = st->coef.a_rho, used_b = st->coef.b_rho;
-    if (lane < S) {
-        double t = level1[lane];
-        for (int b = 1; b < kGroups; ++b) t += level1[(size_t)b * kMaxS + lane];
-        tot[lane] = t;
-    }
-    if (!init_mode) {
-        if (lane < M) {
-            const double x = 0.5 * (nu - lane);  // (nu + 1 - j) / 2 for j = lane + 1
-            sp[0][lane] = cavi::dev_digamma(x);
-            sp[1][lane] = cavi::dev_lgamma(x);
-        } else if (lane == M) {
-            sp[0][M] = cavi::dev_digamma(used_a);
-        } else if (lane == M + 1) {
-            sp[1][M] = cavi::dev_lgamma(used_a);
+    double tot[S];
+    double K0K[M], W[M * M], Ebb[M * M], lndetW = 0.0, trWA = 0.0, trL0W = 0.0, dKWdK = 0.0;
+    bool bad = false;
+    if (wv == 0) {
+        double v = 0.0;
+        if (lane < S) {
+            v = level1[lane];
+            for (int b = 1; b < kGroups; ++b) v += level1[(size_t)b * kMaxS + lane];
         }
+#pragma unroll
+        for (int q = 0; q < S; ++q) tot[q] = __shfl(v, q, 64);
+        if (lane == 0 && !init_mode) {
+            // q(K, Lambda): eqs 24 and 25 with the new q(beta)
+            double Winv[M * M];
+            for (int i = 0; i < M; ++i) K0K[i] = (tot[i] + pr->q0 * pr->K0[i]) / (V + pr->q0);
+            for (int i = 0; i < M; ++i)
+                for (int k = i; k < M; ++k) {
+                    Ebb[i * M + k] = tot[tri(M, i, k)];
+                    Ebb[k * M + i] = tot[tri(M, i, k)];
+                }
+            for (int i = 0; i < M; ++i)
+                for (int k = 0; k < M; ++k)
+                    Winv[i * M + k] = pr->L0inv[i * M + k] + Ebb[i * M + k] + pr->q0 * pr->K0[i] * pr->K0[k]
+                                      - (pr->q0 + V) * K0K[i] * K0K[k];
+            double lndetWinv = 0.0;
+            bad = !spd_inverse<M>(Winv, W, lndetWinv);
+            lndetW = -lndetWinv;
+            for (int i = 0; i < M; ++i)
+                for (int k = 0; k < M; ++k) {
+                    const double A = Ebb[k * M + i] - tot[k] * K0K[i] - K0K[k] * tot[i] + V * K0K[k] * K0K[i];
+                    trWA += W[i * M + k] * A;
+                    trL0W += pr->L0inv[i * M + k] * W[k * M + i];
+                    dKWdK += (K0K[i] - pr->K0[i]) * W[i * M + k] * (K0K[k] - pr->K0[k]);
+                }
+        }
+    } else if (!init_mode && lane <= M) {
+        const double x = lane < M ? 0.5 * (nu - lane) : used_a;  // (nu + 1 - j) / 2 for j = lane + 1
+        if (wv == 1)
+            sp[0][lane] = cavi::dev_digamma(x);
+        else
+            sp[1][lane] = cavi::dev_lgamma(x);
     }
     __syncthreads();
-    if (lane != 0) return;
+    if (threadIdx.x != 0) return;
     const double rho_stat = tot[S - 2];
     if (init_mode) {
         // initial state (Section 3.5) and the coefficients of the first pass
         st->a_rho = pr->a0;
         st->b_rho = pr->b0;
-        double K0K[M], W[M * M];
-        for (int i = 0; i < M; ++i) K0K[i] = 1.0 / (M + 1);
-        for (int i = 0; i < M * M; ++i) W[i] = pr->L0inv[i];
-        for (int i = 0; i < M; ++i) st->K0K[i] = K0K[i];
-        for (int i = 0; i < M * M; ++i) st->W[i] = W[i];
+        double K0[M], W0[M * M];
+        for (int i = 0; i < M; ++i) K0[i] = 1.0 / (M + 1);
+        for (int i = 0; i < M * M; ++i) W0[i] = pr->L0inv[i];
+        for (int i = 0; i < M; ++i) st->K0K[i] = K0[i];
+        for (int i = 0; i < M * M; ++i) st->W[i] = W0[i];
         st->nu = nu;
         st->kappa = kappa;
         st->elbo = 0.0;
@@ -126,24 +157,9 @@ __global__ __launch_bounds__(64) void k_lm_global(Shape sh, State *st, const Pri
         st->swept = 0;
         const double a1 = pr->a0 + 0.5 * V, b1 = pr->b0 + 0.5 * rho_stat;
         st->numeric = isfinite(b1) ? 0 : 1;
-        next_coef<M>(st->coef, a1, b1, W, K0K, nu);
+        next_coef<M>(st->coef, a1, b1, W0, K0, nu);
         return;
     }
-    // q(K, Lambda): eqs 24 and 25 with the new q(beta)
-    double K0K[M], Winv[M * M], W[M * M], Ebb[M * M];
-    for (int i = 0; i < M; ++i) K0K[i] = (tot[i] + pr->q0 * pr->K0[i]) / (V + pr->q0);
-    for (int i = 0; i < M; ++i)
-        for (int k = i; k < M; ++k) {
-            Ebb[i * M + k] = tot[tri(M, i, k)];
-            Ebb[k * M + i] = tot[tri(M, i, k)];
-        }
-    for (int i = 0; i < M; ++i)
-        for (int k = 0; k < M; ++k)
-            Winv[i * M + k] = pr->L0inv[i * M + k] + Ebb[i * M + k] + pr->q0 * pr->K0[i] * pr->K0[k]
-                              - (pr->q0 + V) * K0K[i] * K0K[k];
-    double lndetWinv = 0.0;
-    bool bad = !spd_inverse<M>(Winv, W, lndetWinv);
-    const double lndetW = -lndetWinv;
     // the lower bound at q(rho) of this sweep, the new q(beta) and the new q(K, Lambda)
     const double a = used_a, b = used_b;
     const double Erho = a / b, Elnrho = sp[0][M] - log(b);
@@ -153,14 +169,6 @@ __global__ __launch_bounds__(64) void k_lm_global(Shape sh, State *st, const Pri
         slg += sp[1][j];
     }
     const double ElndetL = sdig + M * kLn2 + lndetW;
-    double trWA = 0.0, trL0W = 0.0, dKWdK = 0.0;
-    for (int i = 0; i < M; ++i)
-        for (int k = 0; k < M; ++k) {
-            const double A = Ebb[k * M + i] - tot[k] * K0K[i] - K0K[k] * tot[i] + V * K0K[k] * K0K[i];
-            trWA += W[i * M + k] * A;
-            trL0W += pr->L0inv[i * M + k] * W[k * M + i];
-            dKWdK += (K0K[i] - pr->K0[i]) * W[i * M + k] * (K0K[k] - pr->K0[k]);
-        }
     const double t_lik = 0.5 * V * Elnrho - 0.5 * V * kLn2Pi - 0.5 * Erho * rho_stat;
     const double t_beta = 0.5 * V * ElndetL - 0.5 * V * M * kLn2Pi - 0.5 * (nu * trWA + V * M / kappa);
     const double t_rho = pr->a0 * log(pr->b0) - pr->lg_a0 + (pr->a0 - 1.0) * Elnrho - pr->b0 * Erho;
@@ -248,7 +256,7 @@ hipError_t launch_sweep(const Shape &sh, const double *r, const double *d, State
 {
     hipLaunchKernelGGL((k_lm_pass<M, false, State>), dim3(sh.nchunk), dim3(kThreads), 0, s, sh, r, d, st, pr, partials);
     launch_lm_reduce(sh, st, 0, partials, level1, s);
-    hipLaunchKernelGGL((k_lm_global<M>), dim3(1), dim3(64), 0, s, sh, st, pr, 0, level1, hist);
+    hipLaunchKernelGGL((k_lm_global<M>), dim3(1), dim3(192), 0, s, sh, st, pr, 0, level1, hist);
     return hipGetLastError();
 }
 
@@ -258,7 +266,7 @@ hipError_t launch_init(const Shape &sh, const double *r, const double *d, State 
 {
     hipLaunchKernelGGL((k_lm_pass<M, true, State>), dim3(sh.nchunk), dim3(kThreads), 0, s, sh, r, d, st, pr, partials);
     launch_lm_reduce(sh, st, 1, partials, level1, s);
-    hipLaunchKernelGGL((k_lm_global<M>), dim3(1), dim3(64), 0, s, sh, st, pr, 1, level1, hist);
+    hipLaunchKernelGGL((k_lm_global<M>), dim3(1), dim3(192), 0, s, sh, st, pr, 1, level1, hist);
     return hipGetLastError();
 }
 
