@@ -699,8 +699,8 @@ def main() -> int:
     ap.add_argument("--save-mlp", default=None, help="c5: save the trained parameters (.npy)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the sweep shards over rows with one "
-              "all-reduce of the statistics per sweep, which this build does not run.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library runs on one GPU; the sweep "
+              "would shard over rows with one all-gather of the statistics per sweep.", file=sys.stderr)
         return 2
     sys.path.insert(0, ROOT)
     if args.workload == "c4":
