@@ -26,7 +26,7 @@ __device__ __forceinline__ double wave_sum(double v)
 
 struct MShared {
     double red[kMBlock / 64];
-    double ak[kMaxK], psi_ak[kMaxK], lg_ak[kMaxK], term_k[kMaxK];
+    double ak[kMaxK], psi_ak[kMaxK], lg_ak[kMaxK], term_k[kMaxK], nk[kMaxK];
     double psi_a[kMaxK], lg_a[kMaxK], ln_bt[kMaxK];  // per component: digamma, lgamma of a_kg; ln(beta_kg / 2 pi)
     double tmp[kMaxKG];
     double asum, psum, lg_asum, lg_prior;
@@ -40,7 +40,9 @@ struct View {
     double *nalpha, *nm, *nbeta, *na, *nb;
     const double *m0;
     float *cc, *hq, *mf;
-    const double *totals;
+    const double *totals;  // nsplit x smax: the sums of the dataset's chunk ranges
+    size_t smax;
+    int nsplit;
     double *hist;
     Ctl *ctl;
 };
@@ -65,10 +67,20 @@ __device__ __forceinline__ View view(const Shape &s, const Bufs &bf, int bi)
     v.cc = bf.cc + kb;
     v.hq = bf.hq + 2 * kg;
     v.mf = bf.mf + kg;
-    v.totals = bf.totals + (size_t)bi * s.Smax;
+    v.totals = bf.totals + (size_t)bi * kRedSplit * s.Smax;
+    v.smax = (size_t)s.Smax;
+    v.nsplit = red_split(bf.ds[bi].nchunk);
     v.hist = bf.hist + (size_t)bi * s.hist_cap;
     v.ctl = bf.ctl + bi;
     return v;
+}
+
+// Statistic i of the dataset: the sums of its chunk ranges, added in range order.
+__device__ __forceinline__ double total(const View &v, int i)
+{
+    double t = v.totals[i];
+    for (int z = 1; z < v.nsplit; ++z) t += v.totals[z * v.smax + i];
+    return t;
 }
 
 // Per-(k,g) coefficients of the E-step from one subpopulation-gene state:
@@ -100,7 +112,7 @@ __device__ __forceinline__ void coef_rows(const View &v, MShared &sh, const Prio
             if (!isfinite(c)) sh.bad = 1;
             if (with_bound) {
                 const double ak = sh.ak[k];
-                sh.term_k[k] = v.totals[k] * elnpi + (p->alpha0 - 1.0) * elnpi + sh.lg_ak[k] - (ak - 1.0) * elnpi;
+                sh.term_k[k] = sh.nk[k] * elnpi + (p->alpha0 - 1.0) * elnpi + sh.lg_ak[k] - (ak - 1.0) * elnpi;
             }
         }
     }
@@ -108,12 +120,14 @@ __device__ __forceinline__ void coef_rows(const View &v, MShared &sh, const Prio
 
 }  // namespace
 
-// totals[b][i] = sum over the chunks of dataset b of partials[chunk][i], in a
-// fixed order: wave v of the block sums a contiguous 1/16 of the chunks (4
-// interleaved accumulators), then the 16 wave sums are added in wave order.
+// totals[b][z][i] = sum over the chunks of range z of dataset b (its chunks [z n / Z, (z + 1) n / Z)
+// for Z = red_split(n)) of partials[chunk][i], in a fixed order: wave v of the block sums a
+// contiguous 1/16 of the range's chunks (4 interleaved accumulators), then the 16 wave sums are added
+// in wave order.  The ranges spread a large dataset over Z workgroups per 64 statistics; the update
+// adds them.
 __global__ __launch_bounds__(kRedBlock) void k_reduce(Shape s, Bufs bf, int init_mode)
 {
-    const int bi = blockIdx.y;
+    const int bi = blockIdx.y, z = blockIdx.z;
     if (!init_mode && sweep_skipped(bf.ctl + bi)) return;
     const Ds d = bf.ds[bi];
     const int S = d.K + 2 * d.K * s.G + 1;
@@ -122,10 +136,14 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce(Shape s, Bufs bf, int init
     const int nw = kRedBlock / 64;
     const int i = blockIdx.x * 64 + lane;
     if (blockIdx.x * 64 >= S) return;
-    const double *pp = bf.partials + (size_t)d.chunk0 * s.Smax;
+    const int Z = red_split(d.nchunk);
+    if (z >= Z) return;
+    const int r0 = (int)(((int64_t)d.nchunk * z) / Z), r1 = (int)(((int64_t)d.nchunk * (z + 1)) / Z);
+    const double *pp = bf.partials + (size_t)(d.chunk0 + r0) * s.Smax;
+    const int nr = r1 - r0;
     double acc = 0.0;
     if (i < S) {
-        const int c0 = (int)(((int64_t)d.nchunk * wv) / nw), c1 = (int)(((int64_t)d.nchunk * (wv + 1)) / nw);
+        const int c0 = (int)(((int64_t)nr * wv) / nw), c1 = (int)(((int64_t)nr * (wv + 1)) / nw);
         double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
         int c = c0;
         for (; c + 4 <= c1; c += 4) {
@@ -142,7 +160,7 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce(Shape s, Bufs bf, int init
     if (wv == 0 && i < S) {
         double t = part[0][lane];
         for (int v = 1; v < nw; ++v) t += part[v][lane];
-        bf.totals[(size_t)bi * s.Smax + i] = t;
+        bf.totals[((size_t)bi * kRedSplit + z) * s.Smax + i] = t;
     }
 }
 
@@ -183,11 +201,11 @@ __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, in
     if (!init_mode && sweep_skipped(ctl)) return;
     __shared__ MShared sh;
     const int G = v.G, K = v.K, KG = K * G, tid = threadIdx.x;
-    const double *T0 = v.totals, *T1 = T0 + K, *T2 = T1 + KG;
-    const double H = T2[KG];
     if (tid == 0) sh.bad = 0;
     if (tid < K) {
-        const double a = p.alpha0 + T0[tid];
+        const double nk = total(v, tid);
+        sh.nk[tid] = nk;
+        const double a = p.alpha0 + nk;
         sh.ak[tid] = a;
         sh.psi_ak[tid] = dev_digamma(a);
         sh.lg_ak[tid] = dev_lgamma(a);
@@ -196,11 +214,12 @@ __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, in
         // a_kg = a0 + N_k / 2 and beta_kg = beta0 + N_k are the same for every gene of a
         // subpopulation: their special functions once per subpopulation, in other waves
         const int k = tid - 64;
-        sh.psi_a[k] = dev_digamma(p.a0 + 0.5 * T0[k]);
-        sh.ln_bt[k] = log((p.beta0 + T0[k]) / kTwoPi);
+        const double nk = total(v, k);
+        sh.psi_a[k] = dev_digamma(p.a0 + 0.5 * nk);
+        sh.ln_bt[k] = log((p.beta0 + nk) / kTwoPi);
     } else if (tid >= 128 && tid < 128 + K) {
         const int k = tid - 128;
-        sh.lg_a[k] = dev_lgamma(p.a0 + 0.5 * T0[k]);
+        sh.lg_a[k] = dev_lgamma(p.a0 + 0.5 * total(v, k));
     }
     __syncthreads();
     const double half_ln_b0 = 0.5 * log(p.beta0 / kTwoPi);
@@ -215,14 +234,15 @@ __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, in
         const int q = tid + it * kMBlock;
         if (q >= KG) break;
         const int k = q / G, g = q - k * G;
-        const double Nk = T0[k];
+        const double Nk = sh.nk[k];
+        const double T1q = total(v, K + q), T2q = total(v, K + KG + q);
         const double c = (double)v.mf[q];
         const double m0p = v.m0[g] - c;
         const double bt = p.beta0 + Nk;
-        const double mp = (p.beta0 * m0p + T1[q]) / bt;
+        const double mp = (p.beta0 * m0p + T1q) / bt;
         const double mm = c + mp;
         const double aa = p.a0 + 0.5 * Nk;
-        double bb = p.b0 + 0.5 * (T2[q] + p.beta0 * m0p * m0p - bt * mp * mp);
+        double bb = p.b0 + 0.5 * (T2q + p.beta0 * m0p * m0p - bt * mp * mp);
         if (bb < p.b0) bb = p.b0;
         nmv[it] = mm;
         nbt[it] = bt;
@@ -231,7 +251,7 @@ __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, in
         const double elt = sh.psi_a[k] - log(bb);
         const double tb = aa / bb;
         if (!init_mode) {
-            double sq = T2[q] - 2.0 * mp * T1[q] + Nk * mp * mp;  // sum r (x - m)^2
+            double sq = T2q - 2.0 * mp * T1q + Nk * mp * mp;  // sum r (x - m)^2
             if (sq < 0.0) sq = 0.0;
             const double dm0 = mp - m0p;                        // m - m0
             acc += 0.5 * (Nk * (elt - kLn2Pi) - tb * sq - Nk / bt);
@@ -240,7 +260,7 @@ __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, in
             acc -= 0.5 * sh.ln_bt[k] + 0.5 * elt - 0.5 + aa * log(bb) - sh.lg_a[k] + (aa - 1.0) * elt - aa;
         }
         sh.tmp[q] = coef_item(v, q, mm, bt, aa, bb, elt);
-        if (!isfinite(mm) || !isfinite(bb) || !isfinite(elt) || !isfinite(T2[q])) bad = 1;
+        if (!isfinite(mm) || !isfinite(bb) || !isfinite(elt) || !isfinite(T2q)) bad = 1;
     }
     if (bad) atomicOr(&sh.bad, 1);
     __syncthreads();
@@ -279,7 +299,7 @@ __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, in
                 ctl->numeric = 1;
             }
         } else {
-            double L = sh.red[0] + H;
+            double L = sh.red[0] + total(v, K + 2 * KG);  // + H, the entropy of the responsibilities
             L += sh.lg_prior - sh.lg_asum;
             for (int k = 0; k < K; ++k) L += sh.term_k[k];
             if (!isfinite(L)) sh.bad = 1;
@@ -312,7 +332,8 @@ __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, in
 
 hipError_t launch_reduce(const Shape &s, const Bufs &b, int init_mode, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce, dim3((s.Smax + 63) / 64, s.B), dim3(kRedBlock), 0, st, s, b, init_mode);
+    const int zmax = red_split((s.Nmax + kChunkRows - 1) / kChunkRows);  // the largest dataset's ranges
+    hipLaunchKernelGGL(k_reduce, dim3((s.Smax + 63) / 64, s.B, zmax), dim3(kRedBlock), 0, st, s, b, init_mode);
     return hipGetLastError();
 }
 
