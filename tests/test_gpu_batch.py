@@ -65,6 +65,28 @@ def test_batch_equals_single_bitwise(torch_cuda, G):
             assert np.array_equal(a, r), f"dataset {b}"
 
 
+def test_batch_equals_single_bitwise_large(torch_cuda):
+    """Datasets of at least 128 chunks are reduced in chunk ranges; in a batch with small datasets
+    they still sum exactly as a single handle does (and the small ones as before)."""
+    from paper_2401_10068_amd.cavi import CaviBatch
+
+    Ns = [2048 * 128 + 123, 300, 2048 * 130, 1000]
+    Ks = [4, 3, 8, 2]
+    G = 16
+    xs, m0 = make_batch(23, Ns, Ks, G)
+    states = [oc.init_standard(X, K, oc.Prior(), m0[b], seed=b) for b, (X, K) in enumerate(zip(xs, Ks))]
+    bt = CaviBatch(torch_cuda.from_numpy(np.concatenate(xs)).cuda(), Ns, Ks, m0=m0)
+    for b, st in enumerate(states):
+        bt.set_state(b, *st.arrays())
+    bt.sweep(5)
+    got = [bt.get_state(b) for b in range(len(Ns))]
+    bt.close()
+    for b, (X, K) in enumerate(zip(xs, Ks)):
+        ref = single(torch_cuda, X, K, m0[b], state=states[b], sweeps=5)
+        for a, r in zip(got[b], ref):
+            assert np.array_equal(a, r), f"dataset {b}"
+
+
 def test_batch_init_matches_single_init(torch_cuda):
     from paper_2401_10068_amd.cavi import CaviBatch
 
