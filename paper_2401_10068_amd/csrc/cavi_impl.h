@@ -16,12 +16,16 @@ namespace cavi {
 // in chunk order, of per-chunk partials; this constant is part of that
 // definition (it fixes the bits), not a tuning knob.
 constexpr int kChunkRows = 2048;
-constexpr int kRedSplit = 4;   // chunk ranges of a large dataset, whose sums the update adds in order
-constexpr int kSplitMinChunks = 128;  // a dataset of at least this many chunks is reduced in kRedSplit ranges
+constexpr int kRedSplit = 4;          // chunk ranges of a large dataset
+constexpr int kSplitMinChunks = 128;  // a dataset of at least this many chunks is large
 
-// Chunk ranges a dataset of nchunk chunks is reduced in: a function of the dataset alone, so that it
-// sums the same way alone and in a batch.
+// Chunk ranges a dataset of nchunk chunks is reduced in (the update adds their sums in order): 4 from
+// 128 chunks up, else 1.  A function of the dataset alone, so that it sums the same way alone and in
+// a batch.  (More ranges make the update's sums slower than the reduction gets faster.)
 __host__ __device__ inline int red_split(int64_t nchunk) { return nchunk >= kSplitMinChunks ? kRedSplit : 1; }
+
+// Ranges of the handle's largest dataset: the stride of the per-dataset range sums.
+__host__ __device__ inline int red_split_max(int64_t Nmax) { return red_split((Nmax + kChunkRows - 1) / kChunkRows); }
 constexpr int kBlock = 256;
 // Responsibilities below exp(-kLogRCut) of the row's normaliser are zero.
 constexpr float kLogRCut = 87.0f;
@@ -83,7 +87,7 @@ struct Bufs {
     float *mf;            // B x Kmax x G     FP32 centre of the statistics
     float *seeds;         // B x Kmax x G     seed rows (initialisation)
     double *partials;     // nchunk x Smax    per-chunk statistics
-    double *totals;       // B x kRedSplit x Smax: per dataset, the sums of each of its red_split(nchunk) chunk ranges
+    double *totals;       // B x red_split_max(Nmax) x Smax: per dataset, the sums of its red_split(nchunk) chunk ranges
     double *hist;         // B x hist_cap     bound after each sweep
     Ctl *ctl;             // B
     int32_t *count;       // 1: datasets still sweeping

@@ -567,7 +567,7 @@ size_t workspace_bytes(const Shape &s)
     n += al(B * G * 8);                // m0
     n += al(K * 4) + al(2 * KG * 4) + 2 * al(KG * 4);  // cc, hq, mf, seeds
     n += al((size_t)s.nchunk * s.Smax * 8);
-    n += al(B * kRedSplit * s.Smax * 8);  // totals
+    n += al(B * red_split_max(s.Nmax) * s.Smax * 8);  // totals
     n += al(B * s.hist_cap * 8);
     n += al(B * sizeof(Ctl)) + al(4);
     n += al((size_t)s.Ntot * 8);
@@ -604,7 +604,7 @@ void carve(const Shape &s, void *ws, Bufs &b)
     b.mf = (float *)take(KG * 4);
     b.seeds = (float *)take(KG * 4);
     b.partials = (double *)take((size_t)s.nchunk * s.Smax * 8);
-    b.totals = (double *)take(B * kRedSplit * s.Smax * 8);
+    b.totals = (double *)take(B * red_split_max(s.Nmax) * s.Smax * 8);
     b.hist = (double *)take(B * s.hist_cap * 8);
     b.ctl = (Ctl *)take(B * sizeof(Ctl));
     b.count = (int32_t *)take(4);

@@ -67,7 +67,7 @@ __device__ __forceinline__ View view(const Shape &s, const Bufs &bf, int bi)
     v.cc = bf.cc + kb;
     v.hq = bf.hq + 2 * kg;
     v.mf = bf.mf + kg;
-    v.totals = bf.totals + (size_t)bi * kRedSplit * s.Smax;
+    v.totals = bf.totals + (size_t)bi * red_split_max(s.Nmax) * s.Smax;
     v.smax = (size_t)s.Smax;
     v.nsplit = red_split(bf.ds[bi].nchunk);
     v.hist = bf.hist + (size_t)bi * s.hist_cap;
@@ -79,7 +79,10 @@ __device__ __forceinline__ View view(const Shape &s, const Bufs &bf, int bi)
 __device__ __forceinline__ double total(const View &v, int i)
 {
     double t = v.totals[i];
-    for (int z = 1; z < v.nsplit; ++z) t += v.totals[z * v.smax + i];
+    if (v.nsplit > 1) {  // kRedSplit ranges: their loads issued together
+#pragma unroll
+        for (int z = 1; z < kRedSplit; ++z) t += v.totals[z * v.smax + i];
+    }
     return t;
 }
 
@@ -160,7 +163,7 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce(Shape s, Bufs bf, int init
     if (wv == 0 && i < S) {
         double t = part[0][lane];
         for (int v = 1; v < nw; ++v) t += part[v][lane];
-        bf.totals[((size_t)bi * kRedSplit + z) * s.Smax + i] = t;
+        bf.totals[((size_t)bi * red_split_max(s.Nmax) + z) * s.Smax + i] = t;
     }
 }
 
@@ -332,8 +335,8 @@ __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, in
 
 hipError_t launch_reduce(const Shape &s, const Bufs &b, int init_mode, hipStream_t st)
 {
-    const int zmax = red_split((s.Nmax + kChunkRows - 1) / kChunkRows);  // the largest dataset's ranges
-    hipLaunchKernelGGL(k_reduce, dim3((s.Smax + 63) / 64, s.B, zmax), dim3(kRedBlock), 0, st, s, b, init_mode);
+    hipLaunchKernelGGL(k_reduce, dim3((s.Smax + 63) / 64, s.B, red_split_max(s.Nmax)), dim3(kRedBlock), 0, st, s, b,
+                       init_mode);
     return hipGetLastError();
 }
 

@@ -66,11 +66,11 @@ def test_batch_equals_single_bitwise(torch_cuda, G):
 
 
 def test_batch_equals_single_bitwise_large(torch_cuda):
-    """Datasets of at least 128 chunks are reduced in chunk ranges; in a batch with small datasets
-    they still sum exactly as a single handle does (and the small ones as before)."""
+    """Datasets of at least 128 chunks are reduced in four chunk ranges; in a batch with small
+    datasets they still sum exactly as a single handle does (and the small ones as before)."""
     from paper_2401_10068_amd.cavi import CaviBatch
 
-    Ns = [2048 * 128 + 123, 300, 2048 * 130, 1000]
+    Ns = [2048 * 250 + 123, 300, 2048 * 370, 1000]
     Ks = [4, 3, 8, 2]
     G = 16
     xs, m0 = make_batch(23, Ns, Ks, G)
