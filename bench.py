@@ -432,7 +432,7 @@ def figs_bench(args) -> int:
     Gibbs sampler, each timed from data already on the device to the last iteration's result on the
     host.  The paper's GTX 1050 and i5-8300H times are printed beside them as context (another
     machine): they are not a target.  At these sizes every kernel lasts a few microseconds, so the
-    runs are bound by launch latency, not by HBM or the ALUs."""
+    runs are bound by the fixed costs of the kernels, not by HBM or the ALUs."""
     import torch
 
     from paper_2401_10068_amd import synth
@@ -486,7 +486,7 @@ def figs_bench(args) -> int:
                                "4000 iterations, Gibbs 10000"},
         "runs": runs,
         "roofline": None,
-        "note": "launch-latency bound: three kernels of a few microseconds per iteration",
+        "note": "bound by the fixed costs of three kernels of a few microseconds per iteration",
         "cpu_baseline": None,
     }
     if not args.no_cpu:
