@@ -162,3 +162,28 @@ def test_full_size_two_iterations(torch_cuda):
     oracle_rows(r, d, c, pr, go.Rng(2), 2, rows)
     compare(h, c, rows, r, d, "V=1e7")
     h.close()
+
+
+def test_chain_ring_wraps(torch_cuda):
+    """The chain keeps its last 65,536 rows in a ring: a read across the wrap equals the same rows
+    read in two pieces, rows no longer kept are refused, and the newest row's rho is the state's."""
+    from paper_2401_10068_amd import cavi
+    from paper_2401_10068_amd.gibbs import LinMixGibbs
+
+    torch = torch_cuda
+    r, d = gen(100, 3)
+    h = LinMixGibbs(torch.from_numpy(r).cuda(), torch.from_numpy(d).cuda(), seed=4)
+    cap = 1 << 16
+    h.iterate(cap + 10)
+    first = cap + 10 - 100
+    rho, K, Lam = h.chain(first, 100)  # rows first+1 .. cap+10: slots cap-90 .. cap-1 and 0 .. 9
+    rho_a, K_a, Lam_a = h.chain(first, 90)
+    rho_b, K_b, Lam_b = h.chain(cap, 10)
+    assert np.array_equal(rho, np.concatenate([rho_a, rho_b]))
+    assert np.array_equal(K, np.concatenate([K_a, K_b])) and np.array_equal(Lam, np.concatenate([Lam_a, Lam_b]))
+    assert rho[-1] == h.state()["rho"]
+    assert np.all(np.isfinite(rho)) and np.all(rho > 0)
+    with pytest.raises(cavi.CaviError) as ei:
+        h.chain(0, 1)  # overwritten
+    assert ei.value.status == cavi.CAVI_E_INVAL
+    h.close()
