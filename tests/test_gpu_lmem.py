@@ -174,3 +174,17 @@ def test_full_size_two_iterations(torch_cuda):
         assert abs(lg[t] - lo_[t]) <= RTOL * scale[t], (t, lg[t], lo_[t], scale[t])
     check(h, p, r, d, "V=1e7", genes=True)
     h.close()
+
+
+def test_long_run_parity(torch_cuda):
+    """1000 iterations (the paper's runs are thousands long): no drift beyond rounding."""
+    from paper_2401_10068_amd.lmem import LinMixEM
+
+    torch = torch_cuda
+    r, d = synth.linmix_dataset(3, 1000, (0.2, 0.3))
+    h = LinMixEM(torch.from_numpy(r).cuda(), torch.from_numpy(d).cuda())
+    lg = h.iterate(1000)
+    p, hist = le.run(r, d, 1000)
+    assert rel(lg, hist) <= RTOL, rel(lg, hist)
+    check(h, p, r, d, "after 1000")
+    h.close()

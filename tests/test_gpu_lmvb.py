@@ -153,3 +153,19 @@ def test_full_size_two_sweeps(torch_cuda):
     scale = max(abs(v) for v in parts.values())
     assert abs(eg[-1] - L) <= RTOL * scale, (eg[-1], L, scale)
     h.close()
+
+
+def test_long_run_parity(torch_cuda):
+    """1000 sweeps (the paper's runs are thousands long): no drift beyond rounding."""
+    from paper_2401_10068_amd.lmvb import LinMixVB
+
+    torch = torch_cuda
+    r, d = synth.linmix_dataset(3, 1000, (0.2, 0.3))
+    pr = lo.default_prior(3)
+    h = LinMixVB(torch.from_numpy(r).cuda(), torch.from_numpy(d).cuda())
+    h.init()
+    eg = h.sweep(1000)
+    s, hist = lo.run(r, d, pr, 1000)
+    assert rel(eg, hist) <= RTOL, rel(eg, hist)
+    check(h, s, r, d, pr, "after 1000")
+    h.close()
