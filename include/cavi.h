@@ -230,6 +230,13 @@ cavi_status cavi_batch_destroy(cavi_batch *bt);
  *              moments, step count kept by the handle).
  *   get/set_params, get_grads: HOST FP32 arrays of n_params entries
  *              (synchronise).
+ *   get_layer: HOST copy (B x dims[layer], row-major FP32; synchronises) of
+ *              what the last call left for linear layer `layer` (1 .. n_hidden
+ *              + 1): what = 0 its pre-activation Z (forward, loss_grad), 1 its
+ *              output Y (for the last layer only after loss_grad, since
+ *              forward writes it to out_dev), 2 the loss gradient w.r.t. Z
+ *              (loss_grad).  Lets each product be checked with the operands
+ *              it was given.
  * B <= max_batch.  Work is enqueued on hip_stream (NULL: the default
  * stream, so that outputs are ordered before a CAVI handle's later work).
  * Not thread-safe.
@@ -250,6 +257,7 @@ cavi_status cavi_mlp_get_grads(cavi_mlp *net, float *host);
 cavi_status cavi_mlp_forward(cavi_mlp *net, const float *feat_dev, int32_t B, float *out_dev);
 cavi_status cavi_mlp_loss_grad(cavi_mlp *net, const float *feat_dev, const float *target_dev, int32_t B,
                                float *loss_host);
+cavi_status cavi_mlp_get_layer(cavi_mlp *net, int32_t layer, int32_t what, int32_t B, float *host);
 cavi_status cavi_mlp_adamw(cavi_mlp *net, float lr, float beta1, float beta2, float eps,
                            float weight_decay);
 cavi_status cavi_mlp_destroy(cavi_mlp *net);

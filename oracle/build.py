@@ -15,7 +15,7 @@ def build(force: bool = True) -> str:
         return LIB
     tmp = LIB + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-                           "-fPIC", "-shared", SRC, "-o", tmp, "-lm"])
+                           "-fopenmp", "-fPIC", "-shared", SRC, "-o", tmp, "-lm"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -38,6 +38,7 @@
  * with -ffp-contract=off.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -315,6 +316,112 @@ double oc_sweep(const float *X, int64_t N, int G, int K, const double *prior, co
     free(xbar);
     free(C);
     return L;
+}
+
+/* The same sweep with the rows split over nthreads contiguous ranges (OpenMP):
+ * each thread forms the S2-S3 responsibilities and entropy of its rows and the
+ * S4 sums over them (first N_k and sum r x, then, after xbar, sum r (x-xbar)^2),
+ * and the per-thread FP64 sums are added in thread order.  With one thread
+ * every sum is taken in row order, as in oc_sweep.  Used to time the oracle on
+ * all host cores and to run it at full workload sizes; the arithmetic per row
+ * is that of oc_estep and oc_stats.  Returns the bound; *used receives the
+ * number of threads that ran (optional). */
+double oc_sweep_mt(const float *X, int64_t N, int G, int K, const double *prior, const double *m0,
+                   double *alpha, double *m, double *beta, double *a, double *b, int nthreads, int *used)
+{
+    if (nthreads < 1) nthreads = 1;
+    const size_t KG = (size_t)K * G;
+    double *elnpi = malloc(sizeof(double) * K);
+    double *tbar = malloc(sizeof(double) * KG);
+    double *elntau = malloc(sizeof(double) * KG);
+    double *r = malloc(sizeof(double) * (size_t)N * K);
+    double *Ht = calloc((size_t)nthreads, sizeof(double));
+    double *Nkt = calloc((size_t)nthreads * K, sizeof(double));
+    double *St = calloc((size_t)nthreads * KG, sizeof(double));
+    double *Ct = calloc((size_t)nthreads * KG, sizeof(double));
+    double *Nk = calloc((size_t)K, sizeof(double));
+    double *xbar = calloc(KG, sizeof(double));
+    double *C = calloc(KG, sizeof(double));
+    int nt_used = 1;
+    oc_expectations(K, G, alpha, a, b, elnpi, tbar, elntau);
+#pragma omp parallel num_threads(nthreads)
+    {
+        const int t = omp_get_thread_num(), nt = omp_get_num_threads();
+        const int64_t lo = N * t / nt, hi = N * (t + 1) / nt;
+        double *l = malloc(sizeof(double) * K);
+        double H = 0.0;
+        for (int64_t n = lo; n < hi; ++n) {
+            const float *x = X + n * G;
+            for (int k = 0; k < K; ++k) {
+                double s = elnpi[k];
+                for (int g = 0; g < G; ++g) {
+                    int i = k * G + g;
+                    double d = (double)x[g] - m[i];
+                    s += 0.5 * (elntau[i] - OC_LN2PI - tbar[i] * d * d - 1.0 / beta[i]);
+                }
+                l[k] = s;
+            }
+            double mx = l[0];
+            for (int k = 1; k < K; ++k)
+                if (l[k] > mx) mx = l[k];
+            double se = 0.0;
+            for (int k = 0; k < K; ++k) se += exp(l[k] - mx);
+            double L = mx + log(se);
+            for (int k = 0; k < K; ++k) {
+                double rk = exp(l[k] - L);
+                r[n * K + k] = rk;
+                H -= rk * (l[k] - L);
+            }
+        }
+        Ht[t] = H;
+        double *nk = Nkt + (size_t)t * K, *sx = St + (size_t)t * KG, *cc = Ct + (size_t)t * KG;
+        for (int64_t n = lo; n < hi; ++n)
+            for (int k = 0; k < K; ++k) {
+                double rk = r[n * K + k];
+                nk[k] += rk;
+                for (int g = 0; g < G; ++g) sx[k * G + g] += rk * (double)X[n * G + g];
+            }
+#pragma omp barrier
+#pragma omp single
+        {
+            nt_used = nt;
+            for (int u = 0; u < nt; ++u)
+                for (int k = 0; k < K; ++k) Nk[k] += Nkt[(size_t)u * K + k];
+            for (int u = 0; u < nt; ++u)
+                for (size_t i = 0; i < KG; ++i) xbar[i] += St[(size_t)u * KG + i];
+            for (int k = 0; k < K; ++k)
+                for (int g = 0; g < G; ++g)
+                    xbar[k * G + g] = Nk[k] > 0.0 ? xbar[k * G + g] / Nk[k] : 0.0;
+        }
+        for (int64_t n = lo; n < hi; ++n)
+            for (int k = 0; k < K; ++k) {
+                double rk = r[n * K + k];
+                for (int g = 0; g < G; ++g) {
+                    double d = (double)X[n * G + g] - xbar[k * G + g];
+                    cc[k * G + g] += rk * d * d;
+                }
+            }
+        free(l);
+    }
+    double H = 0.0;
+    for (int u = 0; u < nt_used; ++u) H += Ht[u];
+    for (int u = 0; u < nt_used; ++u)
+        for (size_t i = 0; i < KG; ++i) C[i] += Ct[(size_t)u * KG + i];
+    oc_update(G, K, prior, m0, Nk, xbar, C, alpha, m, beta, a, b);
+    double Lb = oc_elbo(G, K, prior, m0, Nk, xbar, C, H, alpha, m, beta, a, b);
+    if (used) *used = nt_used;
+    free(elnpi);
+    free(tbar);
+    free(elntau);
+    free(r);
+    free(Ht);
+    free(Nkt);
+    free(St);
+    free(Ct);
+    free(Nk);
+    free(xbar);
+    free(C);
+    return Lb;
 }
 
 /* S7: sweeps until converged or max_sweeps.  elbo_trace[max_sweeps] optional.

@@ -43,6 +43,9 @@ def lib():
         L.oc_elbo_direct.argtypes = [fp, i64, C.c_int, C.c_int, dp, dp, dp, dp, dp, dp, dp, dp]
         L.oc_sweep.restype = C.c_double
         L.oc_sweep.argtypes = [fp, i64, C.c_int, C.c_int, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.oc_sweep_mt.restype = C.c_double
+        L.oc_sweep_mt.argtypes = [fp, i64, C.c_int, C.c_int, dp, dp, dp, dp, dp, dp, dp, C.c_int,
+                                  C.POINTER(C.c_int)]
         L.oc_run.restype = C.c_int
         L.oc_run.argtypes = [fp, i64, C.c_int, C.c_int, dp, dp, dp, dp, dp, dp, dp,
                              C.c_int, C.c_double, dp, C.POINTER(C.c_int)]
@@ -194,6 +197,29 @@ def sweep(X, prior: Prior, m0, st: State, want_r: bool = False):
     L = lib().oc_sweep(_f(X), N, G, st.K, _d(prior.arr()), _d(m0), *st.ptrs(),
                        _d(r) if want_r else None)
     return (L, r) if want_r else L
+
+
+def host_threads() -> int:
+    """Host cores this process may use (its CPU affinity, capped by OMP_NUM_THREADS when set)."""
+    import os
+
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def sweep_mt(X, prior: Prior, m0, st: State, nthreads: int = 0):
+    """One sweep with the rows split over ``nthreads`` threads (all host cores when 0);
+    per-thread FP64 sums added in thread order.  Returns ``(bound, threads used)``."""
+    X = _x(X)
+    N, G = X.shape
+    m0 = np.ascontiguousarray(m0, dtype=np.float64)
+    used = C.c_int(0)
+    L = lib().oc_sweep_mt(_f(X), N, G, st.K, _d(prior.arr()), _d(m0), *st.ptrs(),
+                          int(nthreads or host_threads()), C.byref(used))
+    return L, used.value
 
 
 def run(X, prior: Prior, m0, st: State, max_sweeps: int, tol: float = 1e-6):

@@ -80,6 +80,7 @@ def lib():
             "cavi_mlp_get_grads": (st, [vp, vp]),
             "cavi_mlp_forward": (st, [vp, vp, C.c_int32, vp]),
             "cavi_mlp_loss_grad": (st, [vp, vp, vp, C.c_int32, C.POINTER(C.c_float)]),
+            "cavi_mlp_get_layer": (st, [vp, C.c_int32, C.c_int32, C.c_int32, vp]),
             "cavi_mlp_adamw": (st, [vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float]),
             "cavi_mlp_destroy": (st, [vp]),
             "cavi_last_error": (C.c_char_p, []),
@@ -438,6 +439,12 @@ class CaviMLP:
     def get_grads(self) -> np.ndarray:
         out = np.zeros(self.n_params, dtype=np.float32)
         _check(lib().cavi_mlp_get_grads(self.h, out.ctypes.data))
+        return out
+
+    def get_layer(self, layer: int, what: int, B: int) -> np.ndarray:
+        """Host copy of linear layer ``layer``'s Z (what=0), Y (1) or dLoss/dZ (2), B rows."""
+        out = np.zeros((int(B), self.dims[int(layer)]), dtype=np.float32)
+        _check(lib().cavi_mlp_get_layer(self.h, int(layer), int(what), int(B), out.ctypes.data))
         return out
 
     def forward(self, feat):

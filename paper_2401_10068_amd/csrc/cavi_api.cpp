@@ -40,7 +40,9 @@ cavi_status fail(cavi_status st, const char *fmt, ...)
         if (e_ != hipSuccess) return fail(CAVI_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));     \
     } while (0)
 
-constexpr int kGraphSweeps = 16;  // sweeps per captured graph
+constexpr int kGraphSweeps = 16;  // sweeps per captured graph (the largest of kGraphSizes)
+constexpr int kGraphSizes[] = {16, 8, 4, 2, 1};  // a call of n sweeps replays n's binary digits
+constexpr int kNumGraphs = sizeof(kGraphSizes) / sizeof(kGraphSizes[0]);
 constexpr int kTuneChunks = 2048; // the autotuner times the E-step on at most this many chunks
 constexpr int kHistSingle = 4096; // bounds kept by a single-dataset handle
 
@@ -58,7 +60,7 @@ struct Handle {
     std::vector<Ds> ds;
     std::vector<char> have_state;
     bool coef_dirty = false;
-    hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph[kNumGraphs] = {};  // kGraphSizes[i] sweeps each, captured on first use
     Ctl *hctl = nullptr;        // pinned host mirror of the control blocks
     int32_t *hcount = nullptr;  // pinned
     bool tuned = false;         // E-step schedule chosen (autotuned or set)
@@ -101,7 +103,8 @@ cavi_status make_shape(int32_t B, const int64_t *N, const int32_t *K, int32_t G,
 void destroy_handle(Handle *h)
 {
     if (h->stream) (void)hipStreamSynchronize(h->stream);
-    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    for (hipGraphExec_t g : h->graph)
+        if (g) (void)hipGraphExecDestroy(g);
     if (h->own_ws && h->ws) (void)hipFree(h->ws);
     if (h->hctl) (void)hipHostFree(h->hctl);
     if (h->hcount) (void)hipHostFree(h->hcount);
@@ -325,33 +328,41 @@ cavi_status autotune(Handle *h)
     return CAVI_OK;
 }
 
-cavi_status ensure_graph(Handle *c)
+cavi_status ensure_graph(Handle *c, int gi)
 {
-    if (c->graph) return CAVI_OK;
+    if (c->graph[gi]) return CAVI_OK;
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    cavi_status rs = enqueue_sweeps(c, kGraphSweeps);
+    cavi_status rs = enqueue_sweeps(c, kGraphSizes[gi]);
     hipError_t e = hipStreamEndCapture(c->stream, &g);
     if (rs != CAVI_OK) {
         if (g) (void)hipGraphDestroy(g);
         return rs;
     }
     if (e != hipSuccess) return fail(CAVI_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&c->graph[gi], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-        c->graph = nullptr;
+        c->graph[gi] = nullptr;
         return fail(CAVI_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
     return CAVI_OK;
 }
 
-// Enqueue enough captured sweeps to cover n (the kernels skip past each call's limit).
+// Enqueue exactly n captured sweeps: 16-sweep graphs, then one graph per remaining binary digit
+// of n (8, 4, 2, 1), so that a call never enqueues sweeps past its limit (the kernels would skip
+// them, at the cost of their launches).
 cavi_status replay(Handle *c, int n)
 {
-    cavi_status rs = ensure_graph(c);
-    if (rs != CAVI_OK) return rs;
-    for (int done = 0; done < n; done += kGraphSweeps) HIPCHK(hipGraphLaunch(c->graph, c->stream));
+    for (int gi = 0; gi < kNumGraphs && n > 0; ++gi) {
+        const int sz = kGraphSizes[gi];
+        if (n < sz) continue;
+        cavi_status rs = ensure_graph(c, gi);
+        if (rs != CAVI_OK) return rs;
+        const int reps = gi == 0 ? n / sz : 1;
+        for (int r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(c->graph[gi], c->stream));
+        n -= reps * sz;
+    }
     return CAVI_OK;
 }
 
@@ -570,10 +581,11 @@ static cavi_status get_schedule(Handle *h, int32_t *schedule, float *ms)
 static cavi_status set_schedule(Handle *h, int32_t schedule)
 {
     if (schedule < -1 || schedule > 1) return fail(CAVI_E_INVAL, "schedule=%d outside [-1, 1]", schedule);
-    if (h->graph) {
-        (void)hipGraphExecDestroy(h->graph);
-        h->graph = nullptr;
-    }
+    for (hipGraphExec_t &g : h->graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
     if (schedule == -1) {
         h->tuned = false;
         h->s.schedule = 0;

@@ -54,7 +54,7 @@ struct cavi_mlp {
     bool own_stream = false;
     float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
     std::vector<float *> Z, Y;   // per layer, max_batch x dims[l]
-    float *dA = nullptr, *dB = nullptr;  // max_batch x max dim
+    std::vector<float *> dZ;     // per layer, max_batch x dims[l]: gradient of the loss w.r.t. Z_l
     double *part = nullptr;
     int npart = 0;
 };
@@ -83,12 +83,11 @@ cavi_status cavi_mlp_destroy(cavi_mlp *net)
 {
     if (!net) return CAVI_OK;
     if (net->stream) (void)hipStreamSynchronize(net->stream);
-    for (float *p : {net->params, net->grads, net->m, net->v, net->dA, net->dB})
+    for (float *p : {net->params, net->grads, net->m, net->v})
         if (p) (void)hipFree(p);
-    for (float *p : net->Z)
-        if (p) (void)hipFree(p);
-    for (float *p : net->Y)
-        if (p) (void)hipFree(p);
+    for (const std::vector<float *> *a : {&net->Z, &net->Y, &net->dZ})
+        for (float *p : *a)
+            if (p) (void)hipFree(p);
     if (net->part) (void)hipFree(net->part);
     if (net->own_stream && net->stream) (void)hipStreamDestroy(net->stream);
     delete net;
@@ -108,14 +107,12 @@ cavi_status cavi_mlp_create(cavi_mlp **out, int32_t in_dim, int32_t hidden, int3
     for (int i = 0; i < n_hidden; ++i) n->dims.push_back(hidden);
     n->dims.push_back(out_dim);
     n->max_batch = max_batch;
-    int maxd = 0;
     for (int l = 0; l < n->L; ++l) {
         n->offW.push_back(n->nparams);
         n->nparams += (int64_t)n->dims[l + 1] * n->dims[l];
         n->offb.push_back(n->nparams);
         n->nparams += n->dims[l + 1];
     }
-    for (int d : n->dims) maxd = d > maxd ? d : maxd;
     // parameters: W ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from SplitMix64(seed), b = 0
     std::vector<float> host(n->nparams, 0.f);
     uint64_t s = seed;
@@ -137,14 +134,14 @@ cavi_status cavi_mlp_create(cavi_mlp **out, int32_t in_dim, int32_t hidden, int3
     if (e == hipSuccess) e = hipMalloc(&n->m, pb);
     if (e == hipSuccess) e = hipMalloc(&n->v, pb);
     for (int l = 0; l <= n->L && e == hipSuccess; ++l) {
-        float *z = nullptr, *y = nullptr;
+        float *z = nullptr, *y = nullptr, *dz = nullptr;
         e = hipMalloc(&z, sizeof(float) * (size_t)max_batch * n->dims[l]);
         if (e == hipSuccess) e = hipMalloc(&y, sizeof(float) * (size_t)max_batch * n->dims[l]);
+        if (e == hipSuccess) e = hipMalloc(&dz, sizeof(float) * (size_t)max_batch * n->dims[l]);
         n->Z.push_back(z);
         n->Y.push_back(y);
+        n->dZ.push_back(dz);
     }
-    if (e == hipSuccess) e = hipMalloc(&n->dA, sizeof(float) * (size_t)max_batch * maxd);
-    if (e == hipSuccess) e = hipMalloc(&n->dB, sizeof(float) * (size_t)max_batch * maxd);
     n->npart = (int)(((int64_t)max_batch * out_dim + kBlock - 1) / kBlock);
     if (e == hipSuccess) e = hipMalloc(&n->part, sizeof(double) * n->npart);
     if (e == hipSuccess) e = hipMemcpyAsync(n->params, host.data(), pb, hipMemcpyHostToDevice, n->stream);
@@ -223,23 +220,20 @@ cavi_status cavi_mlp_loss_grad(cavi_mlp *net, const float *feat_dev, const float
     if (st != CAVI_OK) return st;
     const int L = n->L, O = n->dims[L];
     const int cnt = B * O;
-    float *dZ = n->dA, *dY = n->dB;
-    WCHK(launch_mse(cnt, 1.0f / (float)cnt, n->Y[L], target_dev, dZ, n->part, n->stream));
+    WCHK(launch_mse(cnt, 1.0f / (float)cnt, n->Y[L], target_dev, n->dZ[L], n->part, n->stream));
     for (int l = L - 1; l >= 0; --l) {
         const int K = n->dims[l], N = n->dims[l + 1];
         const float *in = l == 0 ? feat_dev : n->Y[l];
+        const float *dZ = n->dZ[l + 1];
         // dW = dZ^T X  [N x K];  db = column sums of dZ
         WCHK(launch_gemm(true, false, N, K, B, dZ, N, in, K, nullptr, n->grads + n->offW[l], nullptr, K, 0,
                          n->stream));
         WCHK(launch_colsum(B, N, dZ, n->grads + n->offb[l], n->stream));
         if (l > 0) {
-            // dX = dZ W  [B x K], then through the GELU of layer l
-            WCHK(launch_gemm(false, false, B, K, N, dZ, N, n->params + n->offW[l], K, nullptr, dY, nullptr, K, 0,
-                             n->stream));
-            WCHK(launch_gelu_back(B * K, n->Z[l], dY, dY, n->stream));
-            float *t = dZ;
-            dZ = dY;
-            dY = t;
+            // dY = dZ W  [B x K], then through the GELU of layer l (in place)
+            WCHK(launch_gemm(false, false, B, K, N, dZ, N, n->params + n->offW[l], K, nullptr, n->dZ[l], nullptr,
+                             K, 0, n->stream));
+            WCHK(launch_gelu_back(B * K, n->Z[l], n->dZ[l], n->dZ[l], n->stream));
         }
     }
     if (loss_host) {
@@ -251,6 +245,19 @@ cavi_status cavi_mlp_loss_grad(cavi_mlp *net, const float *feat_dev, const float
         for (double p : part) s += p;
         *loss_host = (float)(s / cnt);
     }
+    return CAVI_OK;
+}
+
+cavi_status cavi_mlp_get_layer(cavi_mlp *net, int32_t layer, int32_t what, int32_t B, float *host)
+{
+    if (!net || !host) return wfail(CAVI_E_INVAL, "NULL argument");
+    if (layer < 1 || layer > net->L) return wfail(CAVI_E_INVAL, "layer=%d outside [1, %d]", layer, net->L);
+    if (what < 0 || what > 2) return wfail(CAVI_E_INVAL, "what=%d outside [0, 2]", what);
+    if (B < 1 || B > net->max_batch) return wfail(CAVI_E_INVAL, "B=%d outside [1, %d]", B, net->max_batch);
+    const float *src = what == 0 ? net->Z[layer] : what == 1 ? net->Y[layer] : net->dZ[layer];
+    WCHK(hipMemcpyAsync(host, src, sizeof(float) * (size_t)B * net->dims[layer], hipMemcpyDeviceToHost,
+                        net->stream));
+    WCHK(hipStreamSynchronize(net->stream));
     return CAVI_OK;
 }
 

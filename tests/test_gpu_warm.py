@@ -5,12 +5,15 @@ batched CAVI run that starts from it.
 
 Tolerances.  Features: the rank-bin means are the same FP64 sums in the same
 order on both sides (exact); mean and log-variance are FP64 sums in another order, rounded to FP32
-(1 ulp).  MLP: both sides round the same FP32 operands to BF16, so the
-products are exact; the device accumulates in FP32 (relative error about
-K 2^-24 of the sum of |terms|), and an activation that lands within that error
-of a BF16 rounding boundary may round the other way (2^-8 relative of that
-operand).  Outputs and gradients are compared per tensor in the Frobenius
-norm at 3e-3 relative, plus an elementwise bound scaled to the tensor.
+(1 ulp).  MLP, element by element and layer by layer: every product is
+checked on the operands the device was given (its stored inputs, activations
+and output gradients of that layer, read back), which both sides round to
+BF16 identically, so the only differences are the device's FP32 accumulation
+of K exact BF16 products (at most (K + 2) 2^-24 of the sum of |terms| of that
+element) and the FP32 evaluation of bias, GELU, its derivative and the loss
+gradient (a few ulp).  The network's end-to-end output is also compared with
+the oracle's own forward pass, where an activation within the FP32 error of
+a BF16 rounding boundary may round the other way (counted and bounded).
 """
 import numpy as np
 import pytest
@@ -55,6 +58,73 @@ def close_tensor(got, want, rel=3e-3, name=""):
     bound = 0.05 * np.max(np.abs(want)) + 1e-6
     worst = np.max(np.abs(got - want))
     assert worst <= bound, f"{name}: max abs error {worst:.3e} > {bound:.3e}"
+
+
+U32 = 2.0 ** -24
+
+
+def assert_within(got, want, bound, name):
+    got, want = np.asarray(got, np.float64), np.asarray(want, np.float64)
+    err = np.abs(got - want)
+    bad = err > bound + 1e-38
+    assert not bad.any(), (f"{name}: {int(bad.sum())} element(s) outside the bound; worst at "
+                           f"{np.unravel_index(np.argmax(err - bound), err.shape)}: got {got.flat[np.argmax(err - bound)]!r} "
+                           f"want {want.flat[np.argmax(err - bound)]!r}")
+    return float(np.max(err / (bound + 1e-38)))
+
+
+def gelu_grad64(z):
+    return mo.gelu_grad(z)
+
+
+def check_network_per_element(net, params, dims, feat, tgt, loss):
+    """Every kernel of the forward and backward pass, element by element, on the operands it was
+    given (read back from the device), against FP64 products of the same BF16-rounded operands."""
+    B = feat.shape[0]
+    L = len(dims) - 1
+    layers = mo.unpack(params, dims)
+    Z = [None] + [net.get_layer(l, 0, B).astype(np.float64) for l in range(1, L + 1)]
+    Y = [np.asarray(feat, np.float64)] + [net.get_layer(l, 1, B).astype(np.float64) for l in range(1, L + 1)]
+    dZ = [None] + [net.get_layer(l, 2, B).astype(np.float64) for l in range(1, L + 1)]
+    worst = {}
+    for l in range(1, L + 1):
+        W, b = layers[l - 1]
+        Xb, Wb = mo.bf16(Y[l - 1]), mo.bf16(W)
+        exact = Xb @ Wb.T + b
+        mag = np.abs(Xb) @ np.abs(Wb).T + np.abs(b)
+        worst[f"Z{l}"] = assert_within(Z[l], exact, (dims[l - 1] + 2) * U32 * mag, f"forward Z{l}")
+        if l < L:
+            g = mo.gelu(Z[l])
+            worst[f"Y{l}"] = assert_within(Y[l], g, 8 * U32 * np.abs(g) + 4 * U32 * np.abs(Z[l]), f"GELU Y{l}")
+        else:
+            np.testing.assert_array_equal(Y[l], Z[l])
+    cnt = Y[L].size
+    t = np.asarray(tgt, np.float64)
+    want_dz = 2.0 * (Y[L] - t) / cnt
+    worst["dZ_out"] = assert_within(dZ[L], want_dz, 4 * U32 * np.abs(want_dz), "loss gradient")
+    want_loss = float(((Y[L] - t) ** 2).sum() / cnt)
+    assert abs(loss - want_loss) <= 4 * U32 * want_loss, (loss, want_loss)
+    grads = net.get_grads().astype(np.float64)
+    o = 0
+    for l in range(1, L + 1):
+        n_out, n_in = dims[l], dims[l - 1]
+        gW = grads[o:o + n_out * n_in].reshape(n_out, n_in)
+        gb = grads[o + n_out * n_in:o + n_out * n_in + n_out]
+        o += n_out * n_in + n_out
+        dzb, yb = mo.bf16(dZ[l]), mo.bf16(Y[l - 1])
+        worst[f"dW{l}"] = assert_within(gW, dzb.T @ yb, (B + 2) * U32 * (np.abs(dzb).T @ np.abs(yb)), f"dW{l}")
+        db = dZ[l].sum(axis=0)
+        worst[f"db{l}"] = assert_within(gb, db, U32 * np.abs(db) + B * 2.0 ** -52 * np.abs(dZ[l]).sum(0), f"db{l}")
+        if l > 1:
+            W, _ = layers[l - 1]
+            Wb = mo.bf16(W)
+            dy = dzb @ Wb
+            mag = (n_out + 2) * U32 * (np.abs(dzb) @ np.abs(Wb))
+            gp = gelu_grad64(Z[l - 1])
+            want = dy * gp
+            bound = np.abs(gp) * mag + 8 * U32 * (np.abs(dy) + mag) + U32 * np.abs(want)
+            worst[f"dZ{l - 1}"] = assert_within(dZ[l - 1], want, bound, f"dZ{l - 1} (GELU backward)")
+    return worst
 
 
 # ----------------------------------------------------------------------------- features / targets
@@ -114,15 +184,11 @@ def test_mlp_forward_and_gradients(torch_cuda, dims, B):
     want, _, _ = mo.forward(p, dims, feat)
     close_tensor(out, want, 1e-3, "forward")
     loss = net.loss_grad(fd, td)
+    worst = check_network_per_element(net, p, dims, feat, tgt, loss)
+    print("per-element error / bound:", {k: round(v, 3) for k, v in worst.items()})
     wl, wg = mo.loss_grad(p, dims, feat, tgt)
     assert loss == pytest.approx(wl, rel=2e-3)
-    g = net.get_grads()
-    o = 0
-    for l in range(len(dims) - 1):
-        nW, nb = dims[l + 1] * dims[l], dims[l + 1]
-        close_tensor(g[o:o + nW], wg[o:o + nW], 3e-3, f"dW{l}")
-        close_tensor(g[o + nW:o + nW + nb], wg[o + nW:o + nW + nb], 3e-3, f"db{l}")
-        o += nW + nb
+    close_tensor(net.get_grads(), wg, 3e-3, "gradient end to end")
     net.close()
 
 
@@ -140,9 +206,11 @@ def test_mlp_full_size_on_features(torch_cuda):
     fh, th = mo.features(x, off), mo.targets(pi, mu, tau)
     close_tensor(net.forward(feat).cpu().numpy(), mo.forward(p, dims, fh)[0], 1e-3, "forward")
     loss = net.loss_grad(feat, tgt)
+    worst = check_network_per_element(net, p, dims, feat.cpu().numpy(), tgt.cpu().numpy(), loss)
+    print("per-element error / bound:", {k: round(v, 3) for k, v in worst.items()})
     wl, wg = mo.loss_grad(p, dims, fh, th)
     assert loss == pytest.approx(wl, rel=2e-3)
-    close_tensor(net.get_grads(), wg, 3e-3, "gradient")
+    close_tensor(net.get_grads(), wg, 3e-3, "gradient end to end")
     net.close()
 
 

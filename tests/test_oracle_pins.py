@@ -387,3 +387,30 @@ def test_recovers_seeded_proportions_on_small_workload():
     assert np.all(np.abs(Epi[list(perm)] - pi) <= 3 * np.sqrt(pi * (1 - pi) / N) + 2.0 / N)
     Nk = st.alpha[list(perm)] - pr.alpha0
     assert np.all(np.abs(st.m[list(perm)] - mu) <= 4 / np.sqrt(tau * Nk[:, None]))
+
+
+@pytest.mark.parametrize("nthreads", [1, 3, 8])
+def test_threaded_sweep_equals_serial_sweep(nthreads):
+    """The all-core sweep (rows split over threads, per-thread FP64 sums added in thread
+    order) is the serial sweep up to the order of its sums: bitwise with one thread, and
+    within 1e-12 of each array's scale with several (on overlapping, soft clusters)."""
+    X, _ = blobs(21, 5003, 7, 4, sep=2.0, sd=0.8)
+    pr = oc.Prior()
+    m0 = oc.data_mean(X)
+    rng = np.random.default_rng(4)
+    st0 = random_state(rng, 4, 7, X)
+    ser = st0.copy()
+    par = st0.copy()
+    for _ in range(3):
+        Ls = oc.sweep(X, pr, m0, ser)
+        Lp, used = oc.sweep_mt(X, pr, m0, par, nthreads)
+        assert used == nthreads
+        if nthreads == 1:
+            assert Lp == Ls
+        else:
+            assert abs(Lp - Ls) <= 1e-12 * abs(Ls)
+    for a, b in zip(par.arrays(), ser.arrays()):
+        if nthreads == 1:
+            np.testing.assert_array_equal(a, b)
+        else:
+            assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
