@@ -106,30 +106,39 @@ def cpu_baseline(x_host, K: int, seed: int, budget_s: float):
 
 
 def copy_reference(device) -> dict:
-    """Achievable HBM rates on this GPU: a device-to-device copy (bytes read + written) and a
-    read-only sum, each over 1.5 GB (far beyond the caches), best of five, timed with events."""
+    """Achievable HBM rates on this GPU, over 1.5 GB (far beyond the caches): a device-to-device
+    copy (torch; bytes read + written, best of five, timed with events) and the library's plain
+    streaming read (cavi_probe_read, 16-byte loads; the best of a few grid sizes)."""
     import torch
+
+    from paper_2401_10068_amd.cavi import cavi_probe_read
 
     n = 384_000_000
     src = torch.ones(n, dtype=torch.float32, device=device)
     dst = torch.empty_like(src)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-
-    def best(fn):
-        fn()
-        ts = []
-        for _ in range(5):
-            e0.record()
-            fn()
-            e1.record()
-            e1.synchronize()
-            ts.append(e0.elapsed_time(e1) * 1e-3)
-        return min(ts)
-
-    tc = best(lambda: dst.copy_(src))
-    tr = best(lambda: torch.sum(src))
-    del src, dst
-    return {"copy_GBps": 2 * 4 * n / tc / 1e9, "read_GBps": 4 * n / tr / 1e9, "bytes": 4 * n}
+    dst.copy_(src)
+    ts = []
+    for _ in range(5):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    tc = min(ts)
+    del dst
+    out = torch.zeros(16384, dtype=torch.float32, device=device)
+    reads = {}
+    for grid in (1024, 2048, 4096, 8192, 16384):
+        ms = cavi_probe_read(src, out, grid, 5)
+        reads[grid] = 4 * n / (ms * 1e-3) / 1e9
+    torch.cuda.synchronize()
+    ok = abs(float(out[:16384].double().sum()) - n) <= 1e-6 * n  # every float read once
+    del src, out
+    best = max(reads, key=reads.get)
+    return {"copy_GBps": 2 * 4 * n / tc / 1e9, "read_GBps": reads[best], "read_grid": best,
+            "read_GBps_by_grid": {str(k): round(v, 1) for k, v in reads.items()}, "read_sum_ok": ok,
+            "bytes": 4 * n}
 
 
 def lm_bench(args) -> int:

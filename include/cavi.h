@@ -134,6 +134,17 @@ cavi_status cavi_profile_estep(cavi_ctx *ctx, int32_t reps, float *avg_ms);
 /* Free the handle (and the workspace if library-owned).  NULL is a no-op. */
 cavi_status cavi_destroy(cavi_ctx *ctx);
 
+/* Measurement aid (the achievable-read reference of the roofline): a plain
+ * streaming read of the n floats at x_dev (device, 16-byte aligned, caller-
+ * owned) by grid workgroups of 256 threads with 16-byte loads; out_dev
+ * (caller device memory, grid floats) receives per-workgroup sums.  One
+ * warm-up launch, then reps launches timed with HIP events on hip_stream
+ * (NULL: the null stream); *avg_ms receives the mean milliseconds per launch.
+ * Synchronises the stream.  CAVI_E_INVAL for NULL pointers, n, grid or
+ * reps < 1, or a misaligned x_dev. */
+cavi_status cavi_probe_read(const float *x_dev, int64_t n, float *out_dev, int32_t grid, int32_t reps,
+                            void *hip_stream, float *avg_ms);
+
 /* ------------------------------------------------------------------------
  * Batches: B independent datasets sharing G, swept together (one set of
  * launches per sweep, each dataset with its own convergence test).  The same

@@ -56,6 +56,7 @@ def lib():
             "cavi_get_prior_mean": (st, [vp, dp]),
             "cavi_profile_estep": (st, [vp, C.c_int32, C.POINTER(C.c_float)]),
             "cavi_destroy": (st, [vp]),
+            "cavi_probe_read": (st, [vp, C.c_int64, vp, C.c_int32, C.c_int32, vp, C.POINTER(C.c_float)]),
             "cavi_batch_workspace_bytes": (st, [C.c_int32, vp, vp, C.c_int32, C.POINTER(C.c_size_t)]),
             "cavi_batch_create": (st, [C.POINTER(vp), C.c_int32, vp, vp, vp, C.c_int32, C.POINTER(cavi_prior), vp,
                                        vp, C.c_size_t]),
@@ -195,6 +196,19 @@ def cavi_get_prior_mean(h, G: int):
 def cavi_profile_estep(h, reps: int) -> float:
     ms = C.c_float(0.0)
     _check(lib().cavi_profile_estep(h, int(reps), C.byref(ms)))
+    return float(ms.value)
+
+
+def cavi_probe_read(x, out, grid: int, reps: int, stream=None) -> float:
+    """Mean milliseconds of a plain streaming read of the float tensor ``x`` (device) by ``grid``
+    workgroups; ``out`` is a device float tensor of at least ``grid`` entries."""
+    import torch
+
+    assert x.dtype == torch.float32 and x.is_contiguous() and out.dtype == torch.float32 and out.numel() >= grid
+    ms = C.c_float(0.0)
+    st = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    _check(lib().cavi_probe_read(C.c_void_p(x.data_ptr()), x.numel(), C.c_void_p(out.data_ptr()), int(grid),
+                                 int(reps), C.c_void_p(st), C.byref(ms)))
     return float(ms.value)
 
 

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/cavi.h"
+#include "cavi_host.h"
 #include "cavi_impl.h"
 
 using namespace cavi;
@@ -22,6 +23,10 @@ using namespace cavi;
 namespace {
 
 thread_local std::string g_err;
+
+}  // namespace
+
+namespace cavi {
 
 cavi_status fail(cavi_status st, const char *fmt, ...)
 {
@@ -34,38 +39,7 @@ cavi_status fail(cavi_status st, const char *fmt, ...)
     return st;
 }
 
-#define HIPCHK(expr)                                                                                \
-    do {                                                                                            \
-        hipError_t e_ = (expr);                                                                     \
-        if (e_ != hipSuccess) return fail(CAVI_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));     \
-    } while (0)
-
-constexpr int kGraphSweeps = 16;  // sweeps per captured graph (the largest of kGraphSizes)
-constexpr int kGraphSizes[] = {16, 8, 4, 2, 1};  // a call of n sweeps replays n's binary digits
-constexpr int kNumGraphs = sizeof(kGraphSizes) / sizeof(kGraphSizes[0]);
-constexpr int kTuneChunks = 2048; // the autotuner times the E-step on at most this many chunks
-constexpr int kHistSingle = 4096; // bounds kept by a single-dataset handle
-
-
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
-
-struct Handle {
-    Shape s{};
-    Bufs b{};
-    Prior p{};
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    void *ws = nullptr;
-    bool own_ws = false;
-    std::vector<Ds> ds;
-    std::vector<char> have_state;
-    bool coef_dirty = false;
-    hipGraphExec_t graph[kNumGraphs] = {};  // kGraphSizes[i] sweeps each, captured on first use
-    Ctl *hctl = nullptr;        // pinned host mirror of the control blocks
-    int32_t *hcount = nullptr;  // pinned
-    bool tuned = false;         // E-step schedule chosen (autotuned or set)
-    float sched_ms[2] = {0.f, 0.f};
-};
 
 cavi_status make_shape(int32_t B, const int64_t *N, const int32_t *K, int32_t G, int hist_cap, Shape &s,
                        std::vector<Ds> *ds)
@@ -100,17 +74,6 @@ cavi_status make_shape(int32_t B, const int64_t *N, const int32_t *K, int32_t G,
     return CAVI_OK;
 }
 
-void destroy_handle(Handle *h)
-{
-    if (h->stream) (void)hipStreamSynchronize(h->stream);
-    for (hipGraphExec_t g : h->graph)
-        if (g) (void)hipGraphExecDestroy(g);
-    if (h->own_ws && h->ws) (void)hipFree(h->ws);
-    if (h->hctl) (void)hipHostFree(h->hctl);
-    if (h->hcount) (void)hipHostFree(h->hcount);
-    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
-}
-
 cavi_status check_prior(const cavi_prior *prior, Prior &p)
 {
     cavi_prior pr;
@@ -120,6 +83,45 @@ cavi_status check_prior(const cavi_prior *prior, Prior &p)
         return fail(CAVI_E_INVAL, "prior hyperparameters must be finite and > 0");
     p = Prior{pr.alpha0, pr.beta0, pr.a0, pr.b0};
     return CAVI_OK;
+}
+
+
+}  // namespace cavi
+
+namespace {
+
+constexpr int kGraphSweeps = 16;  // sweeps per captured graph (the largest of kGraphSizes)
+constexpr int kGraphSizes[] = {16, 8, 4, 2, 1};  // a call of n sweeps replays n's binary digits
+constexpr int kNumGraphs = sizeof(kGraphSizes) / sizeof(kGraphSizes[0]);
+constexpr int kTuneChunks = 2048; // the autotuner times the E-step on at most this many chunks
+
+struct Handle {
+    Shape s{};
+    Bufs b{};
+    Prior p{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void *ws = nullptr;
+    bool own_ws = false;
+    std::vector<Ds> ds;
+    std::vector<char> have_state;
+    bool coef_dirty = false;
+    hipGraphExec_t graph[kNumGraphs] = {};  // kGraphSizes[i] sweeps each, captured on first use
+    Ctl *hctl = nullptr;        // pinned host mirror of the control blocks
+    int32_t *hcount = nullptr;  // pinned
+    bool tuned = false;         // E-step schedule chosen (autotuned or set)
+    float sched_ms[2] = {0.f, 0.f};
+};
+
+void destroy_handle(Handle *h)
+{
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (hipGraphExec_t g : h->graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (h->own_ws && h->ws) (void)hipFree(h->ws);
+    if (h->hctl) (void)hipHostFree(h->hctl);
+    if (h->hcount) (void)hipHostFree(h->hcount);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
 }
 
 // Shared create: validation done by the caller except for device resources.
@@ -566,6 +568,29 @@ cavi_status cavi_profile_estep(cavi_ctx *ctx, int32_t reps, float *avg_ms)
     if (rs == CAVI_OK) rs = autotune(h);
     if (rs != CAVI_OK) return rs;
     return time_estep(h, reps, avg_ms);
+}
+
+cavi_status cavi_probe_read(const float *x_dev, int64_t n, float *out_dev, int32_t grid, int32_t reps,
+                            void *hip_stream, float *avg_ms)
+{
+    if (!x_dev || !out_dev || !avg_ms) return fail(CAVI_E_INVAL, "NULL argument");
+    if (n < 1 || grid < 1 || reps < 1) return fail(CAVI_E_INVAL, "n, grid and reps must be >= 1");
+    if (((uintptr_t)x_dev) & 15) return fail(CAVI_E_INVAL, "x_dev is not 16-byte aligned");
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(launch_read_probe(x_dev, n, out_dev, grid, st));  // warm-up
+    HIPCHK(hipEventRecord(e0, st));
+    for (int i = 0; i < reps; ++i) HIPCHK(launch_read_probe(x_dev, n, out_dev, grid, st));
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_ms = t / (float)reps;
+    return CAVI_OK;
 }
 
 static cavi_status get_schedule(Handle *h, int32_t *schedule, float *ms)

@@ -134,6 +134,10 @@ hipError_t launch_count_active(const Shape &s, const Bufs &b, hipStream_t st);
 // per seed and no host synchronisation; leaves the seeds in b.seeds.
 hipError_t launch_kmeanspp(const Shape &s, const Bufs &b, unsigned long long seed, hipStream_t st);
 
+// Plain streaming read of n floats from x (16-byte aligned) by grid workgroups; out receives grid
+// per-workgroup sums.  The achievable-read reference of the roofline.
+hipError_t launch_read_probe(const float *x, int64_t n, float *out, int grid, hipStream_t st);
+
 // Learned warm start (warmstart.hip).
 hipError_t launch_features(const float *x, const int64_t *row_off, int B, int G, float *feat, hipStream_t st);
 hipError_t launch_targets(const double *pi, const double *mu, const double *tau, int B, int K, int G, float *tgt,

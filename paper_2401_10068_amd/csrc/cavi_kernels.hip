@@ -643,6 +643,39 @@ hipError_t prepare_kernels()
     return hipSuccess;
 }
 
+// Plain streaming read of n floats (16-byte loads, grid-stride, four loads in flight per lane);
+// each workgroup writes the sum of what it read so that the loads are kept.
+__global__ __launch_bounds__(kBlock) void k_read_probe(const float4 *__restrict__ x, int64_t n4,
+                                                       const float *__restrict__ tail, int ntail, float *out)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    float acc = 0.f;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (; i + 3 * stride < n4; i += 4 * stride) {
+        const float4 a = x[i], b = x[i + stride], c = x[i + 2 * stride], d = x[i + 3 * stride];
+        acc += ((a.x + b.x) + (c.x + d.x)) + ((a.y + b.y) + (c.y + d.y)) + ((a.z + b.z) + (c.z + d.z)) +
+               ((a.w + b.w) + (c.w + d.w));
+    }
+    for (; i < n4; i += stride) {
+        const float4 a = x[i];
+        acc += (a.x + a.y) + (a.z + a.w);
+    }
+    if (blockIdx.x == 0 && threadIdx.x < ntail) acc += tail[threadIdx.x];
+    __shared__ float red[kBlock / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+hipError_t launch_read_probe(const float *x, int64_t n, float *out, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_read_probe, dim3(grid), dim3(kBlock), 0, st, (const float4 *)x, n / 4, x + (n / 4) * 4,
+                       (int)(n % 4), out);
+    return hipGetLastError();
+}
+
 template <int KT>
 static hipError_t launch_estep_t(const Shape &s, const Bufs &b, int init_mode, hipStream_t st)
 {

@@ -222,3 +222,15 @@ def test_gibbs_symbols_exported_and_argument_checks(L):
     assert LL.gibbs_get_chain(None, 0, 1, None, None, None) == cavi.CAVI_E_INVAL
     assert LL.gibbs_get_genes(None, None) == cavi.CAVI_E_INVAL
     assert LL.gibbs_destroy(None) == cavi.CAVI_OK
+
+
+def test_read_probe_rejects_bad_arguments(L):
+    ms = C.c_float(0.0)
+    p, q = C.c_void_p(0x1000), C.c_void_p(0x2000)
+    assert L.cavi_probe_read(None, 16, q, 1, 1, None, C.byref(ms)) == cavi.CAVI_E_INVAL
+    assert L.cavi_probe_read(p, 0, q, 1, 1, None, C.byref(ms)) == cavi.CAVI_E_INVAL
+    assert L.cavi_probe_read(p, 16, q, 0, 1, None, C.byref(ms)) == cavi.CAVI_E_INVAL
+    assert L.cavi_probe_read(p, 16, q, 1, 0, None, C.byref(ms)) == cavi.CAVI_E_INVAL
+    assert L.cavi_probe_read(C.c_void_p(0x1004), 16, q, 1, 1, None, C.byref(ms)) == cavi.CAVI_E_INVAL
+    assert L.cavi_probe_read(p, 16, None, 1, 1, None, C.byref(ms)) == cavi.CAVI_E_INVAL
+
