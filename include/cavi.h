@@ -288,6 +288,30 @@ cavi_status cavi_set_schedule(cavi_ctx *ctx, int32_t schedule);
 cavi_status cavi_batch_get_schedule(cavi_batch *bt, int32_t *schedule, float *ms);
 cavi_status cavi_batch_set_schedule(cavi_batch *bt, int32_t schedule);
 
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (tight serving loops, code
+ * run where hipMalloc is not allowed): one dataset fitted without a handle or
+ * a workspace.  Standard initialisation (seed), then sweeps until
+ * |L_t - L_{t-1}| <= rel_tol |L_t| or max_sweeps, then the state copied to
+ * the caller's host arrays (alpha: K; m, beta, a, b: K x G, k-major) and
+ * *sweeps / *elbo (may be NULL) set as by cavi_run.  Every device buffer is
+ * carved from one static array of cavi_static_scratch_bytes() (64 MiB) that
+ * each GPU the library runs on holds until the process ends; the call makes
+ * no hipMalloc, hipFree or other allocating call.  x_dev (N x G FP32
+ * row-major, 16-byte aligned) is caller-owned and read only.  Work runs on
+ * hip_stream (NULL: the null stream) and the call returns when it is done.
+ * All calls on one GPU share its array: calls that overlap on one GPU (other
+ * threads, other streams) race and must be serialised by the caller.  Same
+ * kernels, order and results as cavi_create + cavi_init_standard + cavi_run
+ * + cavi_get_state.  Errors as those calls, and CAVI_E_NOMEM when N, G and K
+ * need more scratch than the array holds (the message gives both sizes).
+ * ------------------------------------------------------------------------ */
+size_t cavi_static_scratch_bytes(void);
+cavi_status cavi_fit_static(const float *x_dev, int64_t N, int32_t G, int32_t K, const cavi_prior *prior,
+                            uint64_t seed, int32_t max_sweeps, double rel_tol, void *hip_stream,
+                            double *alpha, double *m, double *beta, double *a, double *b,
+                            int32_t *sweeps, double *elbo);
+
 /* Thread-local text of the last error ("" if none). */
 const char *cavi_last_error(void);
 

@@ -30,7 +30,7 @@ COMMON = [
 
 LIBS = {
     "libcavi.so": ["cavi_kernels.hip", "estep_tiled.hip", "update.hip", "warmstart.hip", "lmvb.hip", "lmem.hip",
-                   "gibbs.hip", "cavi_api.cpp", "warmstart_api.cpp"],
+                   "gibbs.hip", "cavi_static.hip", "cavi_api.cpp", "warmstart_api.cpp"],
     "libcavi_synth.so": ["synth.hip"],
 }
 

@@ -56,6 +56,9 @@ def lib():
             "cavi_get_prior_mean": (st, [vp, dp]),
             "cavi_profile_estep": (st, [vp, C.c_int32, C.POINTER(C.c_float)]),
             "cavi_destroy": (st, [vp]),
+            "cavi_static_scratch_bytes": (C.c_size_t, []),
+            "cavi_fit_static": (st, [vp, C.c_int64, C.c_int32, C.c_int32, C.POINTER(cavi_prior), C.c_uint64, C.c_int32,
+                                     C.c_double, vp, dp, dp, dp, dp, dp, C.POINTER(C.c_int32), dp]),
             "cavi_probe_read": (st, [vp, C.c_int64, vp, C.c_int32, C.c_int32, vp, C.POINTER(C.c_float)]),
             "cavi_batch_workspace_bytes": (st, [C.c_int32, vp, vp, C.c_int32, C.POINTER(C.c_size_t)]),
             "cavi_batch_create": (st, [C.POINTER(vp), C.c_int32, vp, vp, vp, C.c_int32, C.POINTER(cavi_prior), vp,

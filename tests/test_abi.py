@@ -234,3 +234,20 @@ def test_read_probe_rejects_bad_arguments(L):
     assert L.cavi_probe_read(C.c_void_p(0x1004), 16, q, 1, 1, None, C.byref(ms)) == cavi.CAVI_E_INVAL
     assert L.cavi_probe_read(p, 16, None, 1, 1, None, C.byref(ms)) == cavi.CAVI_E_INVAL
 
+
+def test_static_fit_rejects_bad_arguments_and_oversize(L):
+    """cavi_fit_static checks its arguments and its scratch need before touching the device."""
+    a = (C.c_double * 64)()
+    p = C.c_void_p(0x1000)
+    args = lambda x, N, G, K, ms=10, tol=1e-6: (x, N, G, K, None, C.c_uint64(0), ms, C.c_double(tol), None,
+                                                a, a, a, a, a, None, None)
+    assert L.cavi_fit_static(*args(None, 1000, 16, 3)) == cavi.CAVI_E_INVAL
+    assert L.cavi_fit_static(*args(C.c_void_p(0x1004), 1000, 16, 3)) == cavi.CAVI_E_INVAL
+    assert L.cavi_fit_static(*args(p, 2, 16, 3)) == cavi.CAVI_E_INVAL
+    assert L.cavi_fit_static(*args(p, 1000, 16, 3, ms=0)) == cavi.CAVI_E_INVAL
+    assert L.cavi_fit_static(*args(p, 1000, 16, 3, tol=-1.0)) == cavi.CAVI_E_INVAL
+    L.cavi_static_scratch_bytes.restype = C.c_size_t
+    assert L.cavi_static_scratch_bytes() == 64 << 20
+    assert L.cavi_fit_static(*args(p, 10_000_000, 96, 8)) == cavi.CAVI_E_NOMEM
+    msg = cavi.cavi_last_error()
+    assert "scratch" in msg and str(64 << 20) in msg
