@@ -751,6 +751,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2", choices=["small", "c2", "c3", "c4", "c5", "lm", "em", "gibbs", "figs"])
+    ap.add_argument("--schedule", type=int, default=None, choices=[0, 1],
+                    help="single-dataset workloads: force an E-step schedule (default: the autotuner's choice)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
     ap.add_argument("--copy-ref", action="store_true",
@@ -791,6 +793,8 @@ def main() -> int:
     x, _, _, _, _ = synth.make_dataset_gpu(seed, 0, N, rec)
     torch.cuda.synchronize()
     cx = Cavi(x, K)
+    if args.schedule is not None:
+        cx.set_schedule(args.schedule)
     cx.init_standard(seed)
     if args.warmup:
         cx.sweep(args.warmup, want_elbo=False)

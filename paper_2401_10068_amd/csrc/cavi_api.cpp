@@ -41,6 +41,9 @@ cavi_status fail(cavi_status st, const char *fmt, ...)
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
+constexpr int64_t kBatchChunkGrid = 2048;  // E-step workgroups of a batch launch
+constexpr int32_t kBatchDatasetGrid = 512;  // datasets a batch's reduction and update take at once
+
 cavi_status make_shape(int32_t B, const int64_t *N, const int32_t *K, int32_t G, int hist_cap, Shape &s,
                        std::vector<Ds> *ds)
 {
@@ -69,6 +72,9 @@ cavi_status make_shape(int32_t B, const int64_t *N, const int32_t *K, int32_t G,
     s.nchunk = (int32_t)nchunk;
     s.tile_rows = choose_tile_rows(G, s.kt);
     s.hist_cap = hist_cap;
+    // batches: capped grids that loop over the work lists (a single dataset: one workgroup per chunk)
+    s.egrid = B > 1 ? (int32_t)std::min<int64_t>(nchunk, kBatchChunkGrid) : (int32_t)nchunk;
+    s.dgrid = B > 1 ? std::min(B, kBatchDatasetGrid) : 1;
     s.Ntot = ntot;
     s.Nmax = nmax;
     return CAVI_OK;
@@ -180,6 +186,7 @@ cavi_status create_handle(Handle *h, const float *x_dev, int32_t B, const int64_
     else
         HIPCHK(launch_prior_mean(h->s, h->b, h->stream));
     HIPCHK(launch_ctl_begin(h->s, h->b, 0, 0, 0.0, 1, h->stream));
+    HIPCHK(launch_list_all(h->s, h->b, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     h->have_state.assign(B, 0);
     return CAVI_OK;
@@ -247,6 +254,7 @@ cavi_status finish_init(Handle *h)
     const Shape &s = h->s;
     const Bufs &B = h->b;
     HIPCHK(hipMemcpyAsync(B.mf, B.seeds, sizeof(float) * s.B * s.Kmax * s.G, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(launch_list_all(s, B, h->stream));
     HIPCHK(launch_estep_stats(s, B, 1, h->stream));
     HIPCHK(launch_reduce(s, B, 1, h->stream));
     HIPCHK(launch_mstep(s, B, h->p, 1, h->stream));
@@ -273,6 +281,7 @@ cavi_status enqueue_sweeps(Handle *c, int n)
         HIPCHK(launch_estep_stats(c->s, c->b, 0, c->stream));
         HIPCHK(launch_reduce(c->s, c->b, 0, c->stream));
         HIPCHK(launch_mstep(c->s, c->b, c->p, 0, c->stream));
+        if (c->s.B > 1) HIPCHK(launch_compact(c->s, c->b, c->stream));
     }
     return CAVI_OK;
 }
@@ -283,6 +292,8 @@ cavi_status time_estep(Handle *h, int reps, float *ms, int max_chunks = 0)
 {
     Shape sh = h->s;
     if (max_chunks > 0 && sh.nchunk > max_chunks) sh.nchunk = max_chunks;
+    sh.egrid = std::min(sh.egrid, sh.nchunk);
+    HIPCHK(launch_list_all(h->s, h->b, h->stream));
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -392,6 +403,7 @@ cavi_status sweep_n(Handle *h, int32_t n, double *elbo_host)
     while (done < n) {
         const int seg = std::min(n - done, elbo_host ? cap : n - done);
         HIPCHK(launch_ctl_begin(h->s, h->b, seg, 0, 0.0, 0, h->stream));
+        HIPCHK(launch_list_all(h->s, h->b, h->stream));
         rs = replay(h, seg);
         if (rs != CAVI_OK) return rs;
         if (elbo_host)
@@ -415,6 +427,7 @@ cavi_status run_all(Handle *h, int32_t max_sweeps, double rel_tol)
     if (rs == CAVI_OK) rs = autotune(h);  // before the control blocks are set for this call
     if (rs != CAVI_OK) return rs;
     HIPCHK(launch_ctl_begin(h->s, h->b, max_sweeps, 1, rel_tol, 0, h->stream));
+    HIPCHK(launch_list_all(h->s, h->b, h->stream));
     int issued = 0;
     int batch = 1;  // graphs between host checks, doubled up to 8
     for (;;) {

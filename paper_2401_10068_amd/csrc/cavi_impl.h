@@ -69,6 +69,8 @@ struct Shape {
     int32_t tile_rows;  // rows per LDS tile of the generic kernel
     int32_t hist_cap;   // bounds kept per dataset
     int32_t schedule;   // tiled E-step schedule: 0 register-heavy, 1 register-light (autotuned)
+    int32_t egrid;      // workgroups of an E-step launch (batches: a capped grid over the work list)
+    int32_t dgrid;      // workgroups per statistic block of the reduction and of the update (batches)
     int64_t Ntot;       // rows of all datasets
     int64_t Nmax;       // rows of the largest dataset
 };
@@ -95,7 +97,22 @@ struct Bufs {
     double *blockmax;     // nchunk           (initialisation)
     unsigned long long *blocksum;  // nchunk  (initialisation)
     double *colpart;      // nchunk x G      (prior centre)
+    int32_t *act_n;       // 2: datasets and chunks on the work lists (batches)
+    int32_t *act_ds;      // B: datasets that still sweep, ascending
+    int32_t *act_chunk;   // nchunk: their chunks, ascending
 };
+
+// Work lists of a batch: after every sweep the datasets that still sweep, and their chunks, are
+// listed, so that the next sweep's launches (capped grids that loop over the lists) spend nothing
+// on finished datasets.  A single-dataset handle takes its chunks directly.  Entries past a
+// dataset's end of sweeping are skipped by sweep_skipped() as before, so a stale list is safe.
+__device__ __forceinline__ int n_active_chunks(const Shape &s, const Bufs &b)
+{
+    return s.B == 1 ? s.nchunk : min(s.nchunk, b.act_n[1]);
+}
+__device__ __forceinline__ int active_chunk(const Shape &s, const Bufs &b, int i) { return s.B == 1 ? i : b.act_chunk[i]; }
+__device__ __forceinline__ int n_active_datasets(const Shape &s, const Bufs &b) { return s.B == 1 ? 1 : min(s.B, b.act_n[0]); }
+__device__ __forceinline__ int active_dataset(const Shape &s, const Bufs &b, int i) { return s.B == 1 ? 0 : b.act_ds[i]; }
 
 __device__ __forceinline__ bool sweep_skipped(const Ctl *c)
 {
@@ -130,6 +147,10 @@ hipError_t launch_resp(const Shape &s, const Bufs &b, float *r, hipStream_t st);
 hipError_t launch_ctl_begin(const Shape &s, const Bufs &b, int max_call, int stop_on_conv, double tol, int reset,
                             hipStream_t st);
 hipError_t launch_count_active(const Shape &s, const Bufs &b, hipStream_t st);
+// Work lists: every dataset and chunk (before a call's first sweep), or the datasets that still
+// sweep and their chunks (after each sweep of a batch).
+hipError_t launch_list_all(const Shape &s, const Bufs &b, hipStream_t st);
+hipError_t launch_compact(const Shape &s, const Bufs &b, hipStream_t st);
 // k-means++ seeds of every dataset (dataset b: SplitMix64 state seed + b), a few launches
 // per seed and no host synchronisation; leaves the seeds in b.seeds.
 hipError_t launch_kmeanspp(const Shape &s, const Bufs &b, unsigned long long seed, hipStream_t st);

@@ -103,7 +103,9 @@ __global__ __launch_bounds__(kBlock) void k_estep_stats(Shape s, Bufs bf, int in
     float *rs = smem + TR * XS;
     const int tid = threadIdx.x;
 
-    for (int chunk = blockIdx.x; chunk < s.nchunk; chunk += gridDim.x) {
+    const int nact = n_active_chunks(s, bf);
+    for (int slot = blockIdx.x; slot < nact; slot += gridDim.x) {
+        const int chunk = active_chunk(s, bf, slot);
         const int bi = bf.chunk_ds[chunk];
         const Ds d = bf.ds[bi];
         if (!init_mode && sweep_skipped(bf.ctl + bi)) continue;
@@ -265,6 +267,53 @@ __global__ void k_count_active(int B, const Ctl *ctl, int32_t *count)
         __syncthreads();
     }
     if (threadIdx.x == 0) *count = red[0];
+}
+
+__global__ void k_list_all(Shape s, Bufs bf)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        bf.act_n[0] = s.B;
+        bf.act_n[1] = s.nchunk;
+    }
+    if (i < s.B) bf.act_ds[i] = i;
+    if (i < s.nchunk) bf.act_chunk[i] = i;
+}
+
+// The datasets that will sweep again and their chunks, in ascending order (one workgroup: each
+// thread takes a contiguous range of datasets; exclusive scans of their counts give the offsets).
+__global__ __launch_bounds__(1024) void k_compact(Shape s, Bufs bf)
+{
+    __shared__ int sd[1024], sc[1024];
+    const int t = threadIdx.x, per = (s.B + 1023) / 1024;
+    const int b0 = min(s.B, t * per), b1 = min(s.B, b0 + per);
+    int nd = 0, nc = 0;
+    for (int b = b0; b < b1; ++b)
+        if (!sweep_skipped(bf.ctl + b)) {
+            ++nd;
+            nc += bf.ds[b].nchunk;
+        }
+    sd[t] = nd;
+    sc[t] = nc;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // inclusive scans (Hillis-Steele)
+        const int ad = t >= off ? sd[t - off] : 0, ac = t >= off ? sc[t - off] : 0;
+        __syncthreads();
+        sd[t] += ad;
+        sc[t] += ac;
+        __syncthreads();
+    }
+    int od = sd[t] - nd, oc = sc[t] - nc;
+    for (int b = b0; b < b1; ++b)
+        if (!sweep_skipped(bf.ctl + b)) {
+            bf.act_ds[od++] = b;
+            const Ds d = bf.ds[b];
+            for (int c = 0; c < d.nchunk; ++c) bf.act_chunk[oc++] = d.chunk0 + c;
+        }
+    if (t == 1023) {
+        bf.act_n[0] = sd[1023];
+        bf.act_n[1] = sc[1023];
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -573,6 +622,7 @@ size_t workspace_bytes(const Shape &s)
     n += al((size_t)s.Ntot * 8);
     n += 2 * al(nblk * 8);
     n += al((size_t)s.nchunk * G * 8);
+    n += al(2 * 4) + al(B * 4) + al((size_t)s.nchunk * 4);  // work lists
     return n;
 }
 
@@ -612,6 +662,9 @@ void carve(const Shape &s, void *ws, Bufs &b)
     b.blockmax = (double *)take(nblk * 8);
     b.blocksum = (unsigned long long *)take(nblk * 8);
     b.colpart = (double *)take((size_t)s.nchunk * G * 8);
+    b.act_n = (int32_t *)take(2 * 4);
+    b.act_ds = (int32_t *)take(B * 4);
+    b.act_chunk = (int32_t *)take((size_t)s.nchunk * 4);
 }
 
 int g_lds_limit = 0;
@@ -680,7 +733,7 @@ template <int KT>
 static hipError_t launch_estep_t(const Shape &s, const Bufs &b, int init_mode, hipStream_t st)
 {
     const size_t lds = (size_t)s.tile_rows * (s.G + 1 + KT + 1) * sizeof(float);
-    hipLaunchKernelGGL(k_estep_stats<KT>, dim3(s.nchunk), dim3(kBlock), lds, st, s, b, init_mode);
+    hipLaunchKernelGGL(k_estep_stats<KT>, dim3(s.egrid), dim3(kBlock), lds, st, s, b, init_mode);
     return hipGetLastError();
 }
 
@@ -743,6 +796,19 @@ hipError_t launch_ctl_begin(const Shape &s, const Bufs &b, int max_call, int sto
 hipError_t launch_count_active(const Shape &s, const Bufs &b, hipStream_t st)
 {
     hipLaunchKernelGGL(k_count_active, dim3(1), dim3(kBlock), 0, st, s.B, b.ctl, b.count);
+    return hipGetLastError();
+}
+
+hipError_t launch_list_all(const Shape &s, const Bufs &b, hipStream_t st)
+{
+    const int n = s.nchunk > s.B ? s.nchunk : s.B;
+    hipLaunchKernelGGL(k_list_all, dim3((n + 255) / 256), dim3(256), 0, st, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const Shape &s, const Bufs &b, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, st, s, b);
     return hipGetLastError();
 }
 

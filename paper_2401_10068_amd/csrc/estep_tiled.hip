@@ -205,7 +205,9 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
     const int jl = lane & 31, half = lane >> 5;
     const float *__restrict__ x = bf.x;
 
-    for (int chunk = blockIdx.x; chunk < s.nchunk; chunk += gridDim.x) {
+    const int nact = n_active_chunks(s, bf);
+    for (int slot = blockIdx.x; slot < nact; slot += gridDim.x) {
+        const int chunk = active_chunk(s, bf, slot);
         const int bi = bf.chunk_ds[chunk];
         const Ds d = bf.ds[bi];
         if (!INIT && sweep_skipped(bf.ctl + bi)) continue;
@@ -640,11 +642,11 @@ hipError_t launch_t(const Shape &s, const Bufs &b, int init_mode, hipStream_t st
 {
     constexpr int lds = Cfg<KT, G>::LDS_BYTES;
     if (init_mode)
-        hipLaunchKernelGGL((k_estep_tiled<KT, G, true, true>), dim3(s.nchunk), dim3(kBlock), lds, st, s, b);
+        hipLaunchKernelGGL((k_estep_tiled<KT, G, true, true>), dim3(s.egrid), dim3(kBlock), lds, st, s, b);
     else if (s.schedule == 1)
-        hipLaunchKernelGGL((k_estep_tiled<KT, G, false, true>), dim3(s.nchunk), dim3(kBlock), lds, st, s, b);
+        hipLaunchKernelGGL((k_estep_tiled<KT, G, false, true>), dim3(s.egrid), dim3(kBlock), lds, st, s, b);
     else
-        hipLaunchKernelGGL((k_estep_tiled<KT, G, false, false>), dim3(s.nchunk), dim3(kBlock), lds, st, s, b);
+        hipLaunchKernelGGL((k_estep_tiled<KT, G, false, false>), dim3(s.egrid), dim3(kBlock), lds, st, s, b);
     return hipGetLastError();
 }
 

@@ -130,40 +130,45 @@ __device__ __forceinline__ void coef_rows(const View &v, MShared &sh, const Prio
 // adds them.
 __global__ __launch_bounds__(kRedBlock) void k_reduce(Shape s, Bufs bf, int init_mode)
 {
-    const int bi = blockIdx.y, z = blockIdx.z;
-    if (!init_mode && sweep_skipped(bf.ctl + bi)) return;
-    const Ds d = bf.ds[bi];
-    const int S = d.K + 2 * d.K * s.G + 1;
     __shared__ double part[kRedBlock / 64][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int nw = kRedBlock / 64;
     const int i = blockIdx.x * 64 + lane;
-    if (blockIdx.x * 64 >= S) return;
-    const int Z = red_split(d.nchunk);
-    if (z >= Z) return;
-    const int r0 = (int)(((int64_t)d.nchunk * z) / Z), r1 = (int)(((int64_t)d.nchunk * (z + 1)) / Z);
-    const double *pp = bf.partials + (size_t)(d.chunk0 + r0) * s.Smax;
-    const int nr = r1 - r0;
-    double acc = 0.0;
-    if (i < S) {
-        const int c0 = (int)(((int64_t)nr * wv) / nw), c1 = (int)(((int64_t)nr * (wv + 1)) / nw);
-        double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
-        int c = c0;
-        for (; c + 4 <= c1; c += 4) {
-            q0 += pp[(size_t)c * s.Smax + i];
-            q1 += pp[(size_t)(c + 1) * s.Smax + i];
-            q2 += pp[(size_t)(c + 2) * s.Smax + i];
-            q3 += pp[(size_t)(c + 3) * s.Smax + i];
+    const int z = blockIdx.z;
+    const int nds = n_active_datasets(s, bf);
+    for (int slot = blockIdx.y; slot < nds; slot += gridDim.y) {
+        const int bi = active_dataset(s, bf, slot);
+        if (!init_mode && sweep_skipped(bf.ctl + bi)) continue;
+        const Ds d = bf.ds[bi];
+        const int S = d.K + 2 * d.K * s.G + 1;
+        if (blockIdx.x * 64 >= S) continue;
+        const int Z = red_split(d.nchunk);
+        if (z >= Z) continue;
+        const int r0 = (int)(((int64_t)d.nchunk * z) / Z), r1 = (int)(((int64_t)d.nchunk * (z + 1)) / Z);
+        const double *pp = bf.partials + (size_t)(d.chunk0 + r0) * s.Smax;
+        const int nr = r1 - r0;
+        double acc = 0.0;
+        if (i < S) {
+            const int c0 = (int)(((int64_t)nr * wv) / nw), c1 = (int)(((int64_t)nr * (wv + 1)) / nw);
+            double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+            int c = c0;
+            for (; c + 4 <= c1; c += 4) {
+                q0 += pp[(size_t)c * s.Smax + i];
+                q1 += pp[(size_t)(c + 1) * s.Smax + i];
+                q2 += pp[(size_t)(c + 2) * s.Smax + i];
+                q3 += pp[(size_t)(c + 3) * s.Smax + i];
+            }
+            for (; c < c1; ++c) q0 += pp[(size_t)c * s.Smax + i];
+            acc = (q0 + q1) + (q2 + q3);
         }
-        for (; c < c1; ++c) q0 += pp[(size_t)c * s.Smax + i];
-        acc = (q0 + q1) + (q2 + q3);
-    }
-    part[wv][lane] = acc;
-    __syncthreads();
-    if (wv == 0 && i < S) {
-        double t = part[0][lane];
-        for (int v = 1; v < nw; ++v) t += part[v][lane];
-        bf.totals[((size_t)bi * red_split_max(s.Nmax) + z) * s.Smax + i] = t;
+        part[wv][lane] = acc;
+        __syncthreads();
+        if (wv == 0 && i < S) {
+            double t = part[0][lane];
+            for (int v = 1; v < nw; ++v) t += part[v][lane];
+            bf.totals[((size_t)bi * red_split_max(s.Nmax) + z) * s.Smax + i] = t;
+        }
+        __syncthreads();  // part is rewritten by the next dataset
     }
 }
 
@@ -197,12 +202,12 @@ __global__ __launch_bounds__(kMBlock) void k_coef(Shape s, Bufs bf)
 // then the lower bound at the new q(pi), q(mu, tau) with the entropy H of the
 // responsibilities.  A non-finite value leaves the state untouched and raises
 // ctl->numeric.
-__global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, int init_mode)
+__device__ __forceinline__ void mstep_one(const Shape &s, const Bufs &bf, const Prior &p, int init_mode, int bi,
+                                          MShared &sh)
 {
-    const View v = view(s, bf, blockIdx.x);
+    const View v = view(s, bf, bi);
     Ctl *ctl = v.ctl;
     if (!init_mode && sweep_skipped(ctl)) return;
-    __shared__ MShared sh;
     const int G = v.G, K = v.K, KG = K * G, tid = threadIdx.x;
     if (tid == 0) sh.bad = 0;
     if (tid < K) {
@@ -333,16 +338,26 @@ __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, in
     }
 }
 
+__global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, int init_mode)
+{
+    __shared__ MShared sh;
+    const int nds = n_active_datasets(s, bf);
+    for (int slot = blockIdx.x; slot < nds; slot += gridDim.x) {
+        mstep_one(s, bf, p, init_mode, active_dataset(s, bf, slot), sh);
+        __syncthreads();  // sh is rewritten by the next dataset
+    }
+}
+
 hipError_t launch_reduce(const Shape &s, const Bufs &b, int init_mode, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce, dim3((s.Smax + 63) / 64, s.B, red_split_max(s.Nmax)), dim3(kRedBlock), 0, st, s, b,
-                       init_mode);
+    hipLaunchKernelGGL(k_reduce, dim3((s.Smax + 63) / 64, s.dgrid, red_split_max(s.Nmax)), dim3(kRedBlock), 0, st, s,
+                       b, init_mode);
     return hipGetLastError();
 }
 
 hipError_t launch_mstep(const Shape &s, const Bufs &b, const Prior &p, int init_mode, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mstep, dim3(s.B), dim3(kMBlock), 0, st, s, b, p, init_mode);
+    hipLaunchKernelGGL(k_mstep, dim3(s.dgrid), dim3(kMBlock), 0, st, s, b, p, init_mode);
     return hipGetLastError();
 }
 
