@@ -618,7 +618,10 @@ static cavi_status get_schedule(Handle *h, int32_t *schedule, float *ms)
 
 static cavi_status set_schedule(Handle *h, int32_t schedule)
 {
-    if (schedule < -1 || schedule > 1) return fail(CAVI_E_INVAL, "schedule=%d outside [-1, 1]", schedule);
+    if (schedule < -1 || schedule > 2) return fail(CAVI_E_INVAL, "schedule=%d outside [-1, 2]", schedule);
+    if (schedule == 2 && !(tiled_supported(h->s.Kmax, h->s.G) && h->s.kt == 16))
+        return fail(CAVI_E_INVAL, "schedule 2 (the screen as a matrix product) needs G in {16, 32, 48, 64} and 9 to "
+                                  "16 subpopulations");
     for (hipGraphExec_t &g : h->graph)
         if (g) {
             (void)hipGraphExecDestroy(g);

@@ -192,19 +192,20 @@ __global__ __launch_bounds__(kBlock) void k_estep_stats(Shape s, Bufs bf, int in
                 const int p = tid + it * kBlock;
                 if (it < nit && p < KG) {
                     const int k = p / G, g = p - k * G;
-                    const float c = mfv[it];
-                    float s1 = 0.f, s2 = 0.f;
+                    const double c = (double)mfv[it];
+                    // FP64 sums with exact products (d = x - c formed in FP64), as in the tiled kernel
+                    double s1 = 0.0, s2 = 0.0;
                     for (int j = 0; j < nr; ++j) {
                         const float rr = rs[j * RS + k];
                         if (rr != 0.f) {
-                            const float dd = xs[j * XS + g] - c;
-                            const float w = rr * dd;
+                            const double dd = (double)xs[j * XS + g] - c;
+                            const double w = (double)rr * dd;
                             s1 += w;
-                            s2 = fmaf(w, dd, s2);
+                            s2 = fma(w, dd, s2);
                         }
                     }
-                    a1[it] += (double)s1;
-                    a2[it] += (double)s2;
+                    a1[it] += s1;
+                    a2[it] += s2;
                 }
             }
             if (tid < K) {

@@ -44,6 +44,7 @@ constexpr uint32_t kOneHot = 1u << 31;
 // vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt_hi[15:14])
 constexpr int kWaitVm0 = 0x0F70;
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 template <int KT, int G>
 struct Cfg {
@@ -186,11 +187,48 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// partial sum of (h x + q)^2 over the first GB genes of an LDS row for one subpopulation, in the
+// screen's order (blocks of 4 genes, fused multiply-adds), so that the exact terms built on it are
+// bitwise those of the vector screen
+template <int GB>
+__device__ __forceinline__ float head_sum(const float *xr, const float *pr)
+{
+    float acc = 0.f;
+#pragma unroll
+    for (int gb = 0; gb < GB; gb += 4) {
+        const f4 v = *(const f4 *)(xr + gb);
+        const float *p = pr + 2 * gb;
+        float u;
+        u = fmaf(v.x, p[0], p[1]); acc = fmaf(u, u, acc);
+        u = fmaf(v.y, p[2], p[3]); acc = fmaf(u, u, acc);
+        u = fmaf(v.z, p[4], p[5]); acc = fmaf(u, u, acc);
+        u = fmaf(v.w, p[6], p[7]); acc = fmaf(u, u, acc);
+    }
+    return acc;
+}
+
+// maximum over the 16 lanes of a DPP row (lanes 16 q .. 16 q + 15), in every lane of the row
+__device__ __forceinline__ float row16_max(float v)
+{
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xF, 0xF, false)));  // ror 8
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xF, 0xF, false)));  // ror 4
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x122, 0xF, 0xF, false)));  // ror 2
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x121, 0xF, 0xF, false)));  // ror 1
+    return v;
+}
+
 }  // namespace
 
-template <int KT, int G, bool INIT, bool LOWREG>
-__global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void k_estep_tiled(Shape s, Bufs bf)
+// SCHED: 0 register-heavy, 1 register-light, 2 register-light with the screen as a matrix product
+// (BF16 MFMA, subpopulations 9..16): every schedule gives bitwise the same results.
+template <int KT, int G, bool INIT, int SCHED>
+__global__ __launch_bounds__(kBlock, (SCHED == 1 ? Cfg<KT, G>::LDS_WAVES : 2)) void k_estep_tiled(Shape s, Bufs bf)
 {
+    constexpr bool LOWREG = SCHED != 0;
+    constexpr bool MSCR = SCHED == 2;
+    static_assert(!MSCR || (!INIT && KT == 16 && G % 16 == 0), "matrix screen: 16 subpopulation slots, G a multiple of 16");
     using C = Cfg<KT, G>;
     constexpr int XS = C::XS, LS = C::LS, PS = C::PS, KH = C::KH, GS = C::GS, GB = C::GB, HG = C::HG;
     extern __shared__ __align__(16) float smem[];
@@ -272,6 +310,49 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
             for (int sl = 0; sl < GS; ++sl)
                 if (k >= K || !gown) mfr[k][sl] = 0.f;
 
+        // matrix screen: with x' = x - mu_g (mu: the prior centre, FP32) and q' = q + h mu_g,
+        //   sum_g (h x + q)^2 = sum_g [h^2 x'^2 + 2 h q' x'] + sum_g q'^2,
+        // a product of the rows [x'^2, x'] (BF16) with the coefficients [h^2, 2 h q'] (BF16) on the
+        // matrix cores.  Lane l gives the coefficients of subpopulation l % 16 for genes
+        // 16 s + 4 (l / 16) + e, e < 4 (step s), and the same genes of its row.
+        constexpr int NS = G / 16;
+        float mu4[MSCR ? NS : 1][4];
+        bf16x8 cf[MSCR ? NS : 1], cfm[MSCR ? NS : 1];
+        float cpk = 0.f, e0k = 0.f;
+        if constexpr (MSCR) {
+            const int kq = lane & 15, q4 = 4 * (lane >> 4);
+            float sq = 0.f, wk = 0.f;
+#pragma unroll
+            for (int st = 0; st < NS; ++st) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int g = 16 * st + q4 + e;
+                    const float mu = (float)bf.m0[(size_t)bi * G + g];
+                    mu4[st][e] = mu;
+                    const float h = pt[kq * PS + 2 * g], qq = pt[kq * PS + 2 * g + 1];
+                    const float qp = fmaf(h, mu, qq);
+                    const __bf16 a = (__bf16)(h * h), bb = (__bf16)(2.f * h * qp);
+                    cf[st][2 * e] = a;
+                    cf[st][2 * e + 1] = bb;
+                    cfm[st][2 * e] = a;
+                    cfm[st][2 * e + 1] = __builtin_bit_cast(__bf16, (unsigned short)(__builtin_bit_cast(unsigned short, bb) & 0x7FFFu));
+                    sq = fmaf(qp, qp, sq);
+                    const float t = fabsf(qq) + fabsf(h * mu);
+                    wk = fmaf(t, t, wk);
+                }
+            }
+            // the four lanes of a subpopulation hold disjoint genes: add their sums
+            sq += __shfl_xor(sq, 16, 64);
+            sq += __shfl_xor(sq, 32, 64);
+            wk += __shfl_xor(wk, 16, 64);
+            wk += __shfl_xor(wk, 32, 64);
+            // approximate l = (c - sum q'^2) - D, within e0k + 2^-7 |D|m of the exact FP32 l, where
+            // |D|m is the same product with |2 h q'| and |x'| (the BF16 roundings of both operands,
+            // 2^-8 of each term, dominate; the constant part covers the FP32 roundings)
+            cpk = kq < K ? ccs[kq] - sq : -INFINITY;
+            e0k = kq < K ? 0x1p-14f * (fabsf(ccs[kq]) + sq + wk + 4.f * G) : 0.f;
+        }
+
         float t0[KT], t1[KT][GS], t2[KT][GS];
 #pragma unroll
         for (int k = 0; k < KT; ++k) {
@@ -320,6 +401,57 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
                     mk = (1u << best) | kOneHot;
                 }
             } else {
+            if constexpr (MSCR) {
+            // A'. matrix screen, two 16-row blocks: lane l takes row 16 blk + l % 16 for the data
+            //     and holds l~ of subpopulation l % 16 for rows 16 blk + 4 (l / 16) + v.  Per row:
+            //     candidates = {k : l~_k + E_k >= max_j (l~_j - E_j) - 87} (every k with a nonzero
+            //     responsibility among them), the first k of largest l~_k - E_k; both written to the
+            //     row's slot KT of the l area as (kh << 16) | mask.
+            {
+                const int kq = lane & 15, qg = lane >> 4;
+#pragma unroll
+                for (int blk = 0; blk < 2; ++blk) {
+                    if (16 * blk >= nj) break;
+                    const float *xr0 = xs + (jbase + 16 * blk + kq) * XS + 4 * qg;
+                    f32x4_t dd = {0.f, 0.f, 0.f, 0.f}, dm = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int st = 0; st < NS; ++st) {
+                        const f4 xv = *(const f4 *)(xr0 + 16 * st);
+                        const float p0 = xv.x - mu4[st][0], p1 = xv.y - mu4[st][1];
+                        const float p2 = xv.z - mu4[st][2], p3 = xv.w - mu4[st][3];
+                        bf16x8 ev;
+                        ev[0] = (__bf16)(p0 * p0); ev[1] = (__bf16)p0;
+                        ev[2] = (__bf16)(p1 * p1); ev[3] = (__bf16)p1;
+                        ev[4] = (__bf16)(p2 * p2); ev[5] = (__bf16)p2;
+                        ev[6] = (__bf16)(p3 * p3); ev[7] = (__bf16)p3;
+                        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+                        const u32x4 eu = __builtin_bit_cast(u32x4, ev);
+                        const bf16x8 em = __builtin_bit_cast(bf16x8, eu & (u32x4){0x7FFFFFFFu, 0x7FFFFFFFu, 0x7FFFFFFFu, 0x7FFFFFFFu});
+                        dd = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ev, cf[st], dd, 0, 0, 0);
+                        dm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(em, cfm[st], dm, 0, 0, 0);
+                    }
+                    uint32_t info[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const float lt = cpk - dd[v];
+                        const float ee = fmaf(0x1p-7f, dm[v], e0k);
+                        const float lo = lt - ee, up = lt + ee;
+                        const float mlo = row16_max(lo);
+                        const uint64_t top = __ballot(lo == mlo);
+                        const uint64_t cnd = __ballot(up >= mlo - kLogRCut);
+                        const uint32_t tb = (uint32_t)(top >> (16 * qg)) & 0xFFFFu;
+                        const uint32_t cb = (uint32_t)(cnd >> (16 * qg)) & 0xFFFFu;
+                        // a row without a finite bound (non-finite data) takes subpopulation 0 alone
+                        info[v] = tb ? ((uint32_t)__builtin_ctz(tb) << 16) | cb : 0u;
+                    }
+                    if (kq == 0) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            ((uint32_t *)ls)[(jbase + 16 * blk + 4 * qg + v) * LS + KT] = info[v];
+                    }
+                }
+            }
+            } else {
             // A. screen: partial sums over the first GB genes; lane (row j, half) takes
             //    subpopulations half, half + 2, ...  Every lane writes all of its slots (a
             //    skipped subpopulation k >= K, or a row past the end, leaves a value that is
@@ -350,6 +482,7 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
                     ls[j * LS + k] = acc;
                 }
             }
+            }  // screens
             wave_lds_sync();
 
             // B. exact terms for the candidate subpopulations of row j (lanes jl, jl+32)
@@ -367,36 +500,47 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
                 done = (1u << K) - 1u;
             } else {
                 float U[KT];
-                float best = -INFINITY;
                 int kh = 0;
-                // the row's partial sums and the c_k, read whole (16-byte reads, no branches)
-                float lv[KT], cv[KT];
+                uint32_t cmask = 0;  // matrix screen: the row's candidates
+                if constexpr (MSCR) {
+                    const uint32_t info = act ? ((const uint32_t *)lr)[KT] : 0u;
+                    kh = (int)(info >> 16);
+                    cmask = info & 0xFFFFu;
+                } else {
+                    float best = -INFINITY;
+                    // the row's partial sums and the c_k, read whole (16-byte reads, no branches)
+                    float lv[KT], cv[KT];
 #pragma unroll
-                for (int q = 0; q < KT; q += 4) {
-                    const f4 a = *(const f4 *)(lr + q);
-                    const f4 c = *(const f4 *)(ccs + q);
-                    lv[q] = a.x, lv[q + 1] = a.y, lv[q + 2] = a.z, lv[q + 3] = a.w;
-                    cv[q] = c.x, cv[q + 1] = c.y, cv[q + 2] = c.z, cv[q + 3] = c.w;
-                }
+                    for (int q = 0; q < KT; q += 4) {
+                        const f4 a = *(const f4 *)(lr + q);
+                        const f4 c = *(const f4 *)(ccs + q);
+                        lv[q] = a.x, lv[q + 1] = a.y, lv[q + 2] = a.z, lv[q + 3] = a.w;
+                        cv[q] = c.x, cv[q + 1] = c.y, cv[q + 2] = c.z, cv[q + 3] = c.w;
+                    }
 #pragma unroll
-                for (int k = 0; k < KT; ++k) {
-                    U[k] = (k < K && act) ? cv[k] - lv[k] : -INFINITY;
-                    if (U[k] > best) {
-                        best = U[k];
-                        kh = k;
+                    for (int k = 0; k < KT; ++k) {
+                        U[k] = (k < K && act) ? cv[k] - lv[k] : -INFINITY;
+                        if (U[k] > best) {
+                            best = U[k];
+                            kh = k;
+                        }
                     }
                 }
-                // exact l for the best-bounded subpopulation
-                const float pkh = lr[kh];
+                // exact l for the first subpopulation (the best bounded)
+                const float pkh = MSCR ? (act ? head_sum<GB>(xr, pt + kh * PS) : 0.f) : lr[kh];
                 const float sh = act ? tail_sum<HG, !LOWREG>(xr, pt + kh * PS, GB + half * HG) : 0.f;
                 const float so = __shfl_xor(sh, 32, 64);
                 const float lkh = ccs[kh] - (pkh + (half == 0 ? sh + so : so + sh));
                 kone = kh;
                 lone = lkh;
                 uint32_t cm = 0;
+                if constexpr (MSCR) {
+                    cm = cmask & ~(1u << kh);
+                } else {
 #pragma unroll
-                for (int k = 0; k < KT; ++k)
-                    if (k < K && k != kh && U[k] - lkh >= -kLogRCut) cm |= 1u << k;
+                    for (int k = 0; k < KT; ++k)
+                        if (k < K && k != kh && U[k] - lkh >= -kLogRCut) cm |= 1u << k;
+                }
                 if (!act) cm = 0;
                 __builtin_amdgcn_wave_barrier();
                 if (act && half == 0) lr[kh] = lkh;
@@ -405,7 +549,7 @@ __global__ __launch_bounds__(kBlock, (LOWREG ? Cfg<KT, G>::LDS_WAVES : 2)) void 
                 while (__ballot(cm != 0)) {
                     const bool mine = cm != 0;
                     const int k = mine ? __builtin_ctz(cm) : 0;
-                    const float pk = lr[k];
+                    const float pk = MSCR ? (mine ? head_sum<GB>(xr, pt + k * PS) : 0.f) : lr[k];
                     const float sk = mine ? tail_sum<HG, !LOWREG>(xr, pt + k * PS, GB + half * HG) : 0.f;
                     const float sko = __shfl_xor(sk, 32, 64);
                     __builtin_amdgcn_wave_barrier();
@@ -642,11 +786,18 @@ hipError_t launch_t(const Shape &s, const Bufs &b, int init_mode, hipStream_t st
 {
     constexpr int lds = Cfg<KT, G>::LDS_BYTES;
     if (init_mode)
-        hipLaunchKernelGGL((k_estep_tiled<KT, G, true, true>), dim3(s.egrid), dim3(kBlock), lds, st, s, b);
-    else if (s.schedule == 1)
-        hipLaunchKernelGGL((k_estep_tiled<KT, G, false, true>), dim3(s.egrid), dim3(kBlock), lds, st, s, b);
+        hipLaunchKernelGGL((k_estep_tiled<KT, G, true, 1>), dim3(s.egrid), dim3(kBlock), lds, st, s, b);
+    else if constexpr (KT == 16 && G % 16 == 0) {
+        if (s.schedule == 2)
+            hipLaunchKernelGGL((k_estep_tiled<KT, G, false, 2>), dim3(s.egrid), dim3(kBlock), lds, st, s, b);
+        else if (s.schedule == 1)
+            hipLaunchKernelGGL((k_estep_tiled<KT, G, false, 1>), dim3(s.egrid), dim3(kBlock), lds, st, s, b);
+        else
+            hipLaunchKernelGGL((k_estep_tiled<KT, G, false, 0>), dim3(s.egrid), dim3(kBlock), lds, st, s, b);
+    } else if (s.schedule == 1)
+        hipLaunchKernelGGL((k_estep_tiled<KT, G, false, 1>), dim3(s.egrid), dim3(kBlock), lds, st, s, b);
     else
-        hipLaunchKernelGGL((k_estep_tiled<KT, G, false, false>), dim3(s.egrid), dim3(kBlock), lds, st, s, b);
+        hipLaunchKernelGGL((k_estep_tiled<KT, G, false, 0>), dim3(s.egrid), dim3(kBlock), lds, st, s, b);
     return hipGetLastError();
 }
 

@@ -11,7 +11,7 @@ These tests compare that path, element by element, with the FP64 oracle:
   initialisation (the run the throughput line reports);
 * a K = 16, G = 48 dataset of 130 chunks and a ragged tail (N = 2048 * 130 + 17)
   with four overlapping pairs of subpopulations (soft responsibilities), one and
-  five sweeps in both E-step schedules.
+  five sweeps in each E-step schedule (2: the screen as a matrix product).
 
 Bars as in the other parity tests: 1e-5 relative per element for alpha, m, beta,
 a, b and for the bound after one and five sweeps; after 100 sweeps the bound
@@ -123,7 +123,7 @@ def test_c2_bound_after_100_sweeps(torch_cuda, c2_data):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("schedule", [0, 1, 2])
 def test_k16_g48_130_chunks_overlapping_pairs(torch_cuda, schedule):
     N = 2048 * 130 + 17
     rec = synth.Recipe(K=16, G=48, dir_alpha=1.0, overlap_pairs=4, overlap_sd=0.5)

@@ -316,3 +316,32 @@ def test_schedules_bitwise_equal_and_autotuned(torch_cuda, N, K, G):
     assert pick in (0, 1) and ms[0] > 0 and ms[1] > 0
     np.testing.assert_array_equal(el, results[0][0])
     cx.close()
+
+
+def test_one_sweep_from_the_hard_initial_state_precision_model(torch_cuda):
+    """The statistics are FP32 sums about the previous centre c.  When a subpopulation's mean moves
+    far in one sweep, T2 = sum r (x - c)^2 is much larger than 2 (b - b0) and the update's
+    cancellation amplifies the FP32 rounding: the relative error of b is about 3e-8 times the
+    factor T2 / (2 (b - b0)).  From the hard-assignment initial state of a K = 16 set with
+    overlapping pairs one subpopulation moves 31 standard deviations (factor about 1,200).  Every
+    element must meet 1e-5 + 1e-7 x factor; the elements whose factor is below 50 (all but the moved
+    subpopulation's) the plain 1e-5 bar; m, alpha, beta, a and the bound the plain 1e-5 bar."""
+    N, K, G = 2 * 2048 + 300, 16, 48
+    rec = synth.Recipe(K=K, G=G, dir_alpha=1.0, overlap_pairs=4, overlap_sd=0.5)
+    X, *_ = synth.make_dataset(91, 0, N, rec)
+    pr = oc.Prior()
+    m0 = oc.data_mean(X)
+    st0 = oc.init_standard(X, K, pr, m0, seed=2)
+    r, _, _ = oc.estep(X, st0)
+    c = st0.m.astype(np.float32).astype(np.float64)
+    d = X.astype(np.float64)[:, None, :] - c[None]
+    T2 = np.einsum("nk,nkg->kg", r, d * d)
+    g, ref, Lg, Lo = one_sweep_case(torch_cuda, X, K, st0, m0)
+    factor = T2 / (2.0 * (ref.b - pr.b0))
+    assert factor.max() > 500  # the case this test is about
+    err = np.abs(g[4] - ref.b) / ref.b
+    assert np.all(err <= 1e-5 + 1e-7 * factor), float(np.max(err / (1e-5 + 1e-7 * factor)))
+    assert np.all(err[factor < 50] <= 1e-5)
+    for name, gv, ov in zip(["alpha", "m", "beta", "a"], g[:4], ref.arrays()[:4]):
+        assert rel_err(gv, ov) <= ONE_SWEEP_RTOL, name
+    assert abs(Lg - Lo) <= ONE_SWEEP_RTOL * abs(Lo)
