@@ -652,8 +652,12 @@ def batch_bench(args) -> int:
 def warm_bench(args) -> int:
     """Time to ELBO convergence (1e-6 relative) of 4,096 fresh K=8 datasets: plain GPU CAVI one
     dataset at a time (sample), batched from the standard initialisation, and batched from the
-    learned warm start (features + MLP inference + state conversion inside the timed region).
-    The MLP is trained first on generated datasets (reported separately), or loaded."""
+    learned warm start, for two feature sets side by side (per gene: moments and 16 nearest-rank
+    quantiles, the workload's definition; moments and 16 rank-bin means).  Plain CAVI is the
+    judge: a warm-started dataset is accepted when its bound is within 1e-6 of the plain one (or
+    better); the others fall back to plain CAVI, and the warm start's time to matching bounds is
+    the warm batch (features + MLP + state + run) plus a batched plain run of the rejected
+    datasets.  Each MLP is trained first on generated datasets (reported), or loaded."""
     import numpy as np
     import torch
 
@@ -663,34 +667,38 @@ def warm_bench(args) -> int:
 
     Ns, Ks, rec, seed = synth.batch_workload("c5eval")
     G, K = rec.G, int(Ks[0])
-    ws = WarmStart(G=G, K=K, max_batch=1024, seed=args.mlp_seed)
-    train = None
-    if args.mlp_params:
-        ws.load(args.mlp_params)
-    else:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        losses = ws.train(args.train_datasets, batch=1024, lr=args.lr,
-                          log_every=max(1, args.train_datasets // 1024 // 10),
-                          log=lambda m: print(m, file=sys.stderr, flush=True))
-        torch.cuda.synchronize()
-        train = {"datasets": args.train_datasets, "steps": int(losses.size), "batch": 1024,
-                 "seconds": time.perf_counter() - t0, "loss_first": float(losses[0]),
-                 "loss_last_avg10": float(losses[-10:].mean())}
-        if args.save_mlp:
-            ws.save(args.save_mlp)
+    kinds = ["quantiles", "bins"] if args.features == "both" else [args.features]
+    nets = {}
+    for kind in kinds:
+        ws = WarmStart(G=G, K=K, max_batch=1024, seed=args.mlp_seed, features=kind)
+        train = None
+        if args.mlp_params:
+            ws.load(args.mlp_params.replace("{kind}", kind))
+        else:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            losses = ws.train(args.train_datasets, batch=1024, lr=args.lr,
+                              log_every=max(1, args.train_datasets // 1024 // 10),
+                              log=lambda m, kind=kind: print(f"[{kind}] {m}", file=sys.stderr, flush=True))
+            torch.cuda.synchronize()
+            train = {"datasets": args.train_datasets, "steps": int(losses.size), "batch": 1024,
+                     "seconds": time.perf_counter() - t0, "loss_first": float(losses[0]),
+                     "loss_last_avg10": float(losses[-10:].mean())}
+            if args.save_mlp:
+                ws.save(args.save_mlp.replace("{kind}", kind))
+        nets[kind] = (ws, train)
     x, row_off, _, _, _, _, _ = synth.make_batch_gpu(seed, Ns, Ks, rec)
     off_d = row_off.to(x.device)
     torch.cuda.synchronize()
 
-    def batched(warm: bool):
-        bt = CaviBatch(x, Ns, Ks)
+    def batched(ws, xb, Nb, Kb, offb, seed_b):
+        bt = CaviBatch(xb, Nb, Kb)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        if warm:
-            ws.warm_start(bt, x, off_d)
+        if ws is not None:
+            ws.warm_start(bt, xb, offb)
         else:
-            bt.init_standard(seed)
+            bt.init_standard(seed_b)
         torch.cuda.synchronize()
         t_init = time.perf_counter() - t0
         sw, el, nconv = bt.run(args.max_sweeps, 1e-6)
@@ -701,11 +709,33 @@ def warm_bench(args) -> int:
                 "sweeps_median": float(np.median(sw)), "sweeps_p90": float(np.percentile(sw, 90)),
                 "sweeps_max": int(sw.max())}, sw, el
 
-    plain_b, psw, pel = batched(False)
-    warm_b, wsw, wel = batched(True)
+    plain_b, psw, pel = batched(None, x, Ns, Ks, off_d, seed)
     tol = 1e-6 * np.abs(pel)
-    accepted = wel >= pel - tol
-    better = wel > pel + tol
+    results = {}
+    for kind, (ws, train) in nets.items():
+        warm_b, wsw, wel = batched(ws, x, Ns, Ks, off_d, seed)
+        accepted = wel >= pel - tol
+        better = wel > pel + tol
+        rej = np.flatnonzero(~accepted)
+        fb = {"datasets": int(rej.size), "total_s": 0.0}
+        if rej.size:
+            # the rejected datasets' rows gathered into a batch of their own, plain from the standard
+            # initialisation (the fallback's cost; their plain bounds are those of the plain run)
+            parts = [x[int(row_off[b]):int(row_off[b + 1])] for b in rej]
+            xr = torch.cat(parts, 0).contiguous()
+            offr = torch.from_numpy(np.concatenate([[0], np.cumsum(Ns[rej])]).astype(np.int64)).to(x.device)
+            fb_b, _, _ = batched(None, xr, Ns[rej], Ks[rej], offr, seed)
+            fb.update(fb_b)
+            del xr, parts
+        results[kind] = {
+            "training": train, "batched_warm": warm_b, "fallback_plain": fb,
+            "warm_plus_fallback_s": warm_b["total_s"] + fb["total_s"],
+            "acceptance": {"accepted": int(accepted.sum()), "rate": float(accepted.mean()),
+                           "strictly_better": int(better.sum()), "datasets": int(Ns.size),
+                           "median_rel_elbo_gap": float(np.median((wel - pel) / np.abs(pel)))},
+            "sweeps_accepted_warm_vs_plain": [int(wsw[accepted].sum()), int(psw[accepted].sum())],
+            "speedup_vs_batched_plain": plain_b["total_s"] / (warm_b["total_s"] + fb["total_s"]),
+        }
     idx = np.arange(0, Ns.size, max(1, Ns.size // args.plain_sample))
     t_plain = 0.0
     for b in idx:
@@ -719,10 +749,13 @@ def warm_bench(args) -> int:
         t_plain += time.perf_counter() - t0
         cx.close()
     frac = float(Ns[idx].sum() / Ns.sum())
-    nkg = float((wsw.astype(np.float64) * Ns * K * G).sum())
+    best = max(results, key=lambda k: results[k]["speedup_vs_batched_plain"])
+    nkg = float((psw.astype(np.float64) * Ns * K * G).sum())
     out = {
         "metric": METRIC,
-        "value": nkg / warm_b["total_s"],
+        # the matching bounds are the plain ones: N K G work of the plain sweeps over the best
+        # warm start's time to reach them (warm batch + fallback)
+        "value": nkg / results[best]["warm_plus_fallback_s"],
         "unit": "N*K*G elems/s",
         "n_gpus": 1,
         "higher_is_better": True,
@@ -730,17 +763,14 @@ def warm_bench(args) -> int:
         "dtype": "f32 (MLP: bf16 products, f32 accumulate)",
         "config": {"workload": f"{Ns.size} fresh datasets (c5eval): N log-uniform in [{Ns.min()}, {Ns.max()}], "
                                f"K={K}, G={G}, seed {seed}, run to 1e-6"},
-        "training": train,
         "plain_one_at_a_time": {"sample": int(idx.size), "sample_s": t_plain, "extrapolated_s": t_plain / frac},
         "batched_plain": plain_b,
-        "batched_warm": warm_b,
-        "warm_acceptance": {"accepted": int(accepted.sum()), "strictly_better": int(better.sum()),
-                            "datasets": int(Ns.size),
-                            "median_rel_elbo_gap": float(np.median((wel - pel) / np.abs(pel)))},
-        "speedup_warm_vs_batched_plain": plain_b["total_s"] / warm_b["total_s"],
-        "speedup_warm_vs_plain": (t_plain / frac) / warm_b["total_s"],
+        "warm": results,
+        "best_features": best,
+        "speedup_batched_plain_vs_one_at_a_time": (t_plain / frac) / plain_b["total_s"],
     }
-    ws.close()
+    for ws, _ in nets.values():
+        ws.close()
     print(json.dumps(out), flush=True)
     return 0
 
@@ -751,8 +781,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2", choices=["small", "c2", "c3", "c4", "c5", "lm", "em", "gibbs", "figs"])
-    ap.add_argument("--schedule", type=int, default=None, choices=[0, 1],
-                    help="single-dataset workloads: force an E-step schedule (default: the autotuner's choice)")
+    ap.add_argument("--schedule", type=int, default=None, choices=[0, 1, 2],
+                    help="single-dataset workloads: force an E-step schedule (default: the autotuner's choice; "
+                         "2 = the screen as a BF16 matrix product, K in 9..16)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
     ap.add_argument("--copy-ref", action="store_true",
@@ -763,8 +794,11 @@ def main() -> int:
     ap.add_argument("--train-datasets", type=int, default=1_000_000, help="c5: generated datasets to train on")
     ap.add_argument("--lr", type=float, default=1e-3, help="c5: peak learning rate")
     ap.add_argument("--mlp-seed", type=int, default=0, help="c5: MLP initialisation seed")
-    ap.add_argument("--mlp-params", default=None, help="c5: load trained MLP parameters (.npy) instead of training")
-    ap.add_argument("--save-mlp", default=None, help="c5: save the trained parameters (.npy)")
+    ap.add_argument("--mlp-params", default=None,
+                    help="c5: load trained MLP parameters (.npy; '{kind}' in the path is replaced by the feature set)")
+    ap.add_argument("--save-mlp", default=None, help="c5: save the trained parameters (.npy; '{kind}' as above)")
+    ap.add_argument("--features", default="both", choices=["both", "quantiles", "bins"],
+                    help="c5: warm-start feature sets to train and compare")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library runs on one GPU; the sweep "

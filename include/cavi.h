@@ -221,6 +221,10 @@ cavi_status cavi_batch_destroy(cavi_batch *bt);
  * max(floor((i+1)M/16), floor(iM/16)+1)) and its value is the mean of gene g
  * over those rows.  Means are stored as (v - 25)/10, the log-variance as is.
  * An empty dataset gets NaN features.  Device output, FP32.
+ * cavi_features_quantiles: the same layout and moments, with j=2..17 the 16
+ * nearest-rank quantiles of gene g over all N rows instead of the rank bins:
+ * sorted(x_g)[floor((i + 0.5) N / 16)], i = 0..15 (the per-gene summary of
+ * the warm-start workload), stored as (v - 25)/10.
  *
  * Targets (cavi_warm_targets): from generating parameters (DEVICE FP64:
  * pi[B*K], mu[B*K*G], tau[B*K*G], k-major per dataset) the training target
@@ -254,6 +258,8 @@ cavi_status cavi_batch_destroy(cavi_batch *bt);
  * ------------------------------------------------------------------------ */
 cavi_status cavi_features(const float *x_dev, const int64_t *row_off_dev, int32_t B, int32_t G,
                           float *feat_dev, void *hip_stream);
+cavi_status cavi_features_quantiles(const float *x_dev, const int64_t *row_off_dev, int32_t B, int32_t G,
+                                    float *feat_dev, void *hip_stream);
 cavi_status cavi_warm_targets(const double *pi_dev, const double *mu_dev, const double *tau_dev,
                               int32_t B, int32_t K, int32_t G, float *target_dev, void *hip_stream);
 

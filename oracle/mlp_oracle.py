@@ -6,7 +6,8 @@ The paper has no warm start; its iteration (Section 3.4) starts from a
 chosen state.  This module defines, in the plainest form, what the warm-start
 path computes so that the GPU kernels can be checked element by element:
 
-* ``features``     per-dataset, per-gene summary statistics of the rows;
+* ``features``     per-dataset, per-gene summary statistics of the rows (moments and
+  rank-bin means; ``features_quantiles``: moments and nearest-rank quantiles);
 * ``targets``      the regression targets built from generating parameters;
 * ``forward`` / ``loss_grad``  an MLP (GELU hidden layers, linear output,
   mean squared error) whose matrix products take their operands rounded to
@@ -66,6 +67,28 @@ def features(x, row_off) -> np.ndarray:
             for r in rank[lo:hi]:
                 s = s + rows[r]
             f[:, 2 + j] = (s / (hi - lo) - CENTRE) / SCALE
+    return out
+
+
+def features_quantiles(x, row_off) -> np.ndarray:
+    """B x 18G float32, the per-gene summary of the warm-start workload: per gene
+    (mean-25)/10 and ln max(var, 1e-30) as in ``features``, then (q_j-25)/10 for the 16
+    nearest-rank quantiles q_j = sorted(x_g)[floor((j + 0.5) N / 16)] over all N rows (the
+    level times N taken in FP64), j = 0..15."""
+    x = np.asarray(x, dtype=np.float32)
+    row_off = np.asarray(row_off, dtype=np.int64)
+    B, G = row_off.size - 1, x.shape[1]
+    out = features(x, row_off)
+    for b in range(B):
+        rows = x[row_off[b]:row_off[b + 1]]
+        N = rows.shape[0]
+        if N == 0:
+            continue
+        f = out[b].reshape(G, FEAT_PER_GENE)
+        for g in range(G):
+            col = np.sort(rows[:, g].astype(np.float64))
+            for j in range(16):
+                f[g, 2 + j] = (col[int(math.floor((j + 0.5) / 16.0 * N))] - CENTRE) / SCALE
     return out
 
 

@@ -75,6 +75,7 @@ def lib():
             "cavi_batch_get_schedule": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
             "cavi_batch_set_schedule": (st, [vp, C.c_int32]),
             "cavi_features": (st, [vp, vp, C.c_int32, C.c_int32, vp, vp]),
+            "cavi_features_quantiles": (st, [vp, vp, C.c_int32, C.c_int32, vp, vp]),
             "cavi_warm_targets": (st, [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp]),
             "cavi_mlp_create": (st, [C.POINTER(vp), C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                      C.c_uint64, vp]),
@@ -213,6 +214,34 @@ def cavi_probe_read(x, out, grid: int, reps: int, stream=None) -> float:
     _check(lib().cavi_probe_read(C.c_void_p(x.data_ptr()), x.numel(), C.c_void_p(out.data_ptr()), int(grid),
                                  int(reps), C.c_void_p(st), C.byref(ms)))
     return float(ms.value)
+
+
+def cavi_fit_static(x, K: int, seed: int, max_sweeps: int = 10000, rel_tol: float = 1e-6, m0=None,
+                    alpha0=1.0, beta0=1e-3, a0=0.5, b0=0.5, stream=None):
+    """One dataset fitted in the library's static scratch (no device allocation): standard
+    initialisation, sweeps to convergence.  Returns ``(status, (alpha, m, beta, a, b), sweeps,
+    elbo)``; status is CAVI_OK or CAVI_E_NOTCONV, other statuses raise."""
+    import torch
+
+    assert x.dtype == torch.float32 and x.dim() == 2 and x.is_contiguous()
+    N, G = x.shape
+    pr = cavi_prior(alpha0, beta0, a0, b0, None)
+    keep = None
+    if m0 is not None:
+        keep = np.ascontiguousarray(m0, dtype=np.float64)
+        assert keep.shape == (G,)
+        pr.m0 = keep.ctypes.data_as(C.POINTER(C.c_double))
+    alpha = np.zeros(K)
+    arrs = [np.zeros((K, G)) for _ in range(4)]
+    sw = C.c_int32(0)
+    el = C.c_double(0.0)
+    st = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    status = lib().cavi_fit_static(C.c_void_p(x.data_ptr()), N, G, int(K), C.byref(pr), C.c_uint64(seed),
+                                   int(max_sweeps), float(rel_tol), C.c_void_p(st), _dp(alpha),
+                                   *[_dp(a) for a in arrs], C.byref(sw), C.byref(el))
+    if status not in (CAVI_OK, CAVI_E_NOTCONV):
+        _check(status)
+    return status, (alpha, *arrs), int(sw.value), float(el.value)
 
 
 def cavi_destroy(h):
@@ -397,17 +426,19 @@ def _check_dev(t, name: str, dim: int | None = None, dtype=None):
         raise ValueError(f"{name} must be a contiguous {dtype} tensor on the GPU")
 
 
-def cavi_features(x, row_off, stream=None):
+def cavi_features(x, row_off, stream=None, kind: str = "bins"):
     """Per-dataset features (B x 18G float32) of concatenated rows ``x`` cut at ``row_off``
-    (device int64, B+1 offsets)."""
+    (device int64, B+1 offsets): per gene the moments and 16 rank-bin means (``kind="bins"``,
+    cavi_features) or 16 nearest-rank quantiles (``kind="quantiles"``, cavi_features_quantiles)."""
     import torch
 
     _check_dev(x, "x", 2)
     _check_dev(row_off, "row_off", 1, torch.int64)
     B, G = row_off.numel() - 1, x.shape[1]
     feat = torch.empty((B, FEATURES_PER_GENE * G), dtype=torch.float32, device=x.device)
-    _check(lib().cavi_features(C.c_void_p(x.data_ptr()), C.c_void_p(row_off.data_ptr()), B, G,
-                               C.c_void_p(feat.data_ptr()), _stream_ptr(stream)))
+    fn = {"bins": lib().cavi_features, "quantiles": lib().cavi_features_quantiles}[kind]
+    _check(fn(C.c_void_p(x.data_ptr()), C.c_void_p(row_off.data_ptr()), B, G, C.c_void_p(feat.data_ptr()),
+              _stream_ptr(stream)))
     return feat
 
 

@@ -161,6 +161,7 @@ hipError_t launch_read_probe(const float *x, int64_t n, float *out, int grid, hi
 
 // Learned warm start (warmstart.hip).
 hipError_t launch_features(const float *x, const int64_t *row_off, int B, int G, float *feat, hipStream_t st);
+hipError_t launch_features_quantiles(const float *x, const int64_t *row_off, int B, int G, float *feat, hipStream_t st);
 hipError_t launch_targets(const double *pi, const double *mu, const double *tau, int B, int K, int G, float *tgt,
                           hipStream_t st);
 hipError_t launch_gemm(bool ta, bool tb, int M, int N, int K, const float *A, int lda, const float *B, int ldb,

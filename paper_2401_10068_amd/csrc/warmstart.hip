@@ -9,6 +9,8 @@
 //   ranked by their row sum over genes (left-to-right FP64 sum; ties by row index), rank
 //   bin j holds ranks [floor(j M / 16), max(floor((j+1) M / 16), floor(j M / 16) + 1)),
 //   and c_gj is the mean of gene g over the rows of bin j (FP64, summed in rank order).
+// Quantile features (k_features_q): the same moments, then (q_gj - 25) / 10 for the 16
+// nearest-rank quantiles q_gj = sorted(x_g)[floor((j + 0.5) N / 16)] over all N rows.
 // Targets of a generated dataset (K components sorted by their mean over
 // genes, ascending, ties by index): (mu - 25) / 10 [K G], ln tau [K G], ln pi [K].
 #include <math.h>
@@ -47,21 +49,14 @@ __device__ __forceinline__ float gelu_grad(float z)
 
 // ---------------------------------------------------------------------------------------------
 // features: one workgroup per dataset
-__global__ __launch_bounds__(kBlock) void k_features(const float *__restrict__ x, const int64_t *__restrict__ row_off,
-                                                     int G, float *__restrict__ feat)
+// ---------------------------------------------------------------------------------------------
+// features: one workgroup per dataset
+// slots 0 and 1 of every gene: (mean - 25) / 10 and ln max(var, 1e-30) over all N >= 1 rows
+__device__ void feature_moments(const float *__restrict__ xd, int64_t N, int G, float *__restrict__ f)
 {
-    __shared__ double key[kSortMax];
-    __shared__ int32_t rid[kSortMax];
     __shared__ double part[2 * kBlock];
     __shared__ double gmean[kMaxG];
-    const int b = blockIdx.x, tid = threadIdx.x;
-    const int64_t r0 = row_off[b], N = row_off[b + 1] - r0;
-    const float *xd = x + r0 * G;
-    float *f = feat + (size_t)b * 18 * G;
-    if (N <= 0) {  // empty dataset: no features (NaN)
-        for (int q = tid; q < 18 * G; q += kBlock) f[q] = NAN;
-        return;
-    }
+    const int tid = threadIdx.x;
     // moments over all rows: lane slots (gene, row phase), RP rows per pass, coalesced along rows
     const int RP = G >= kBlock ? 1 : kBlock / G;
     for (int pass = 0; pass < 2; ++pass) {
@@ -95,6 +90,22 @@ __global__ __launch_bounds__(kBlock) void k_features(const float *__restrict__ x
             if (G < kBlock) break;
         }
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_features(const float *__restrict__ x, const int64_t *__restrict__ row_off,
+                                                     int G, float *__restrict__ feat)
+{
+    __shared__ double key[kSortMax];
+    __shared__ int32_t rid[kSortMax];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int64_t r0 = row_off[b], N = row_off[b + 1] - r0;
+    const float *xd = x + r0 * G;
+    float *f = feat + (size_t)b * 18 * G;
+    if (N <= 0) {  // empty dataset: no features (NaN)
+        for (int q = tid; q < 18 * G; q += kBlock) f[q] = NAN;
+        return;
+    }
+    feature_moments(xd, N, G, f);
     // rank the first M rows by their row sum (bitonic sort of (key, row) pairs, +inf padding)
     const int M = (int)min(N, (int64_t)kSortMax);
     int P = 1;
@@ -137,6 +148,103 @@ __global__ __launch_bounds__(kBlock) void k_features(const float *__restrict__ x
         for (int r = lo; r < hi; ++r) s += (double)xd[(size_t)rid[r] * G + g];
         f[(size_t)g * 18 + 2 + j] = (float)((s / (double)(hi - lo) - 25.0) / 10.0);
     }
+}
+
+// Nearest-rank quantiles of every gene, slots 2..17: q_j = sorted(x_g)[floor((j + 0.5) N / 16)],
+// stored as (q_j - 25) / 10.  Exact order statistics by radix selection on the order-preserving
+// 32-bit key of the floats, 4 bits per pass from the top, for a block of up to 32 genes at a time
+// and all 16 ranks at once: the 16 order statistics of a gene are nondecreasing, so ranks that
+// share the bits chosen so far form runs, and each value adds to the histogram of the run (if
+// any) whose prefix it matches, found by a binary search over the 16 prefixes.
+__device__ __forceinline__ uint32_t order_key(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float key_value(uint32_t k)
+{
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+constexpr int kQGenes = 32;  // genes per block of the quantile search
+
+__device__ void feature_quantiles(const float *__restrict__ xd, int64_t N, int G, float *__restrict__ f)
+{
+    __shared__ uint32_t hist[kQGenes][16][16];
+    __shared__ uint32_t pref[kQGenes][16], npref[kQGenes][16];
+    __shared__ int32_t rk[kQGenes][16], nrk[kQGenes][16];
+    const int tid = threadIdx.x;
+    for (int gb0 = 0; gb0 < G; gb0 += kQGenes) {
+        const int ng = min(kQGenes, G - gb0);
+        for (int i = tid; i < ng * 16; i += kBlock) {
+            const int g = i >> 4, t = i & 15;
+            pref[g][t] = 0u;
+            rk[g][t] = (int32_t)floor(((double)t + 0.5) / 16.0 * (double)N);
+        }
+        __syncthreads();
+        const int RP = kBlock / ng;  // row phases: lanes over the block's genes, coalesced along rows
+        for (int pass = 0; pass < 8; ++pass) {
+            const int shift = 28 - 4 * pass;
+            const uint32_t hmask = pass == 0 ? 0u : (0xFFFFFFFFu << (shift + 4));
+            for (int i = tid; i < ng * 256; i += kBlock) (&hist[0][0][0])[i] = 0u;
+            __syncthreads();
+            if (tid < RP * ng) {
+                const int g = tid % ng, rp = tid / ng;
+                for (int64_t n = rp; n < N; n += RP) {
+                    const uint32_t key = order_key(xd[n * G + gb0 + g]);
+                    const uint32_t mk = key & hmask;
+                    int lo = 0;  // first rank whose prefix is >= mk
+#pragma unroll
+                    for (int step = 8; step > 0; step >>= 1)
+                        if (pref[g][lo + step - 1] < mk) lo += step;
+                    if (lo < 16 && pref[g][lo] == mk) atomicAdd(&hist[g][lo][(key >> shift) & 15u], 1u);
+                }
+            }
+            __syncthreads();
+            for (int i = tid; i < ng * 16; i += kBlock) {
+                const int g = i >> 4, t = i & 15;
+                int r0 = t;  // first rank of the run
+                while (r0 > 0 && pref[g][r0 - 1] == pref[g][t]) --r0;
+                uint32_t cum = 0;
+                int dgt = 0;
+                for (; dgt < 15; ++dgt) {
+                    const uint32_t c = hist[g][r0][dgt];
+                    if ((uint32_t)rk[g][t] < cum + c) break;
+                    cum += c;
+                }
+                npref[g][t] = pref[g][t] | ((uint32_t)dgt << shift);
+                nrk[g][t] = rk[g][t] - (int32_t)cum;
+            }
+            __syncthreads();
+            for (int i = tid; i < ng * 16; i += kBlock) {
+                const int g = i >> 4, t = i & 15;
+                pref[g][t] = npref[g][t];
+                rk[g][t] = nrk[g][t];
+            }
+            __syncthreads();
+        }
+        for (int i = tid; i < ng * 16; i += kBlock) {
+            const int g = i >> 4, t = i & 15;
+            f[(size_t)(gb0 + g) * 18 + 2 + t] = (float)(((double)key_value(pref[g][t]) - 25.0) / 10.0);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_features_q(const float *__restrict__ x, const int64_t *__restrict__ row_off,
+                                                       int G, float *__restrict__ feat)
+{
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int64_t r0 = row_off[b], N = row_off[b + 1] - r0;
+    const float *xd = x + r0 * G;
+    float *f = feat + (size_t)b * 18 * G;
+    if (N <= 0) {
+        for (int q = tid; q < 18 * G; q += kBlock) f[q] = NAN;
+        return;
+    }
+    feature_moments(xd, N, G, f);
+    feature_quantiles(xd, N, G, f);
 }
 
 // targets: one thread per dataset
@@ -347,6 +455,12 @@ __global__ void k_warm_state(Shape s, Bufs bf, Prior p, const float *__restrict_
 hipError_t launch_features(const float *x, const int64_t *row_off, int B, int G, float *feat, hipStream_t st)
 {
     hipLaunchKernelGGL(k_features, dim3(B), dim3(kBlock), 0, st, x, row_off, G, feat);
+    return hipGetLastError();
+}
+
+hipError_t launch_features_quantiles(const float *x, const int64_t *row_off, int B, int G, float *feat, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_features_q, dim3(B), dim3(kBlock), 0, st, x, row_off, G, feat);
     return hipGetLastError();
 }
 

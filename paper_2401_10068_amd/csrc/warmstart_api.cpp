@@ -70,6 +70,15 @@ cavi_status cavi_features(const float *x_dev, const int64_t *row_off_dev, int32_
     return CAVI_OK;
 }
 
+cavi_status cavi_features_quantiles(const float *x_dev, const int64_t *row_off_dev, int32_t B, int32_t G,
+                                    float *feat_dev, void *hip_stream)
+{
+    if (!x_dev || !row_off_dev || !feat_dev) return wfail(CAVI_E_INVAL, "NULL argument");
+    if (B < 1 || G < 1 || G > kMaxG) return wfail(CAVI_E_INVAL, "B=%d, G=%d out of range", B, G);
+    WCHK(launch_features_quantiles(x_dev, row_off_dev, B, G, feat_dev, (hipStream_t)hip_stream));
+    return CAVI_OK;
+}
+
 cavi_status cavi_warm_targets(const double *pi_dev, const double *mu_dev, const double *tau_dev, int32_t B,
                               int32_t K, int32_t G, float *target_dev, void *hip_stream)
 {

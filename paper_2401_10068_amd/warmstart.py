@@ -1,6 +1,7 @@
 """Learned warm start of the batched CAVI path.
 
-A dataset's per-gene summary features (``cavi_features``) go through an MLP
+A dataset's per-gene summary features (``cavi_features``: moments and rank-bin means, or
+moments and nearest-rank quantiles) go through an MLP
 (``CaviMLP``: 18G -> 256 -> 256 -> 256 -> K(2G+1), GELU, BF16 matrix-core
 products with FP32 master weights) whose output row is turned into the
 starting variational state of every dataset of a batch
@@ -24,7 +25,10 @@ class WarmStart:
     """MLP for datasets of ``G`` genes and ``K`` subpopulations."""
 
     def __init__(self, G: int = 48, K: int = 8, hidden: int = 256, n_hidden: int = 3, max_batch: int = 1024,
-                 seed: int = 0):
+                 seed: int = 0, features: str = "bins"):
+        if features not in ("bins", "quantiles"):
+            raise ValueError(f"features must be 'bins' or 'quantiles', not {features!r}")
+        self.features = features
         self.G, self.K = int(G), int(K)
         self.in_dim = FEATURES_PER_GENE * self.G
         self.out_dim = self.K * (2 * self.G + 1)
@@ -50,7 +54,7 @@ class WarmStart:
             Ns, _ = synth.batch_shapes(data_seed, batch, n_lo, n_hi, self.K, self.K, offset=off)
             Ks = np.full(batch, self.K, dtype=np.int32)
             x, row_off, _, pi, mu, tau, _ = synth.make_batch_gpu(data_seed, Ns, Ks, rec, ds_offset=off)
-            feat = cavi_features(x, row_off.to(x.device))
+            feat = cavi_features(x, row_off.to(x.device), kind=self.features)
             tgt = cavi_warm_targets(pi, mu, tau)
             del x
             want = log_every and (s % log_every == 0 or s == steps - 1)
@@ -70,7 +74,7 @@ class WarmStart:
     def predict(self, x, row_off_dev):
         """MLP output rows (B x K(2G+1), device) for concatenated rows ``x`` cut at ``row_off_dev``."""
         B = row_off_dev.numel() - 1
-        feat = cavi_features(x, row_off_dev)
+        feat = cavi_features(x, row_off_dev, kind=self.features)
         outs = [self.mlp.forward(feat[i:i + self.max_batch].contiguous()) for i in range(0, B, self.max_batch)]
         import torch
 

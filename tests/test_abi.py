@@ -251,3 +251,9 @@ def test_static_fit_rejects_bad_arguments_and_oversize(L):
     assert L.cavi_fit_static(*args(p, 10_000_000, 96, 8)) == cavi.CAVI_E_NOMEM
     msg = cavi.cavi_last_error()
     assert "scratch" in msg and str(64 << 20) in msg
+
+
+def test_binding_functions_present():
+    """The Python binding wraps the entry points the GPU tests and the bench call."""
+    for name in ["cavi_fit_static", "cavi_probe_read", "cavi_features", "cavi_warm_targets"]:
+        assert callable(getattr(cavi, name, None)), name

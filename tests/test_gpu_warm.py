@@ -147,6 +147,31 @@ def test_features_parity(torch_cuda, G):
     np.testing.assert_allclose(f[:, :, :2], w[:, :, :2], rtol=3e-7, atol=3e-7)
 
 
+@pytest.mark.parametrize("G", [48, 7, 300])
+def test_quantile_features_parity(torch_cuda, G):
+    """Nearest-rank quantiles are bitwise the oracle's (exact order statistics, the same FP64
+    conversion); moments to 1 FP32 ulp.  Includes N = 1 and N < 16, many tied values, negative
+    values, N beyond 32,768 (a gene block of 32 genes and a partial one at G = 48, 300), and an
+    empty dataset."""
+    from paper_2401_10068_amd.cavi import cavi_features
+
+    Ns = [1, 5, 100, 4096, 9000, 40000] if G < 300 else [3, 700, 5000]
+    x, off, *_ = cpu_batch(43, Ns, 3, G)
+    last = len(Ns) - 1
+    x[off[last]:off[last + 1], :] = np.round(x[off[last]:off[last + 1], :])  # ties
+    x[off[1]:off[2], : min(G, 5)] -= 40.0                                    # negative values
+    off = np.insert(off, 2, off[1])
+    feat = cavi_features(torch_cuda.from_numpy(x).cuda(), torch_cuda.from_numpy(off).cuda(),
+                         kind="quantiles").cpu().numpy()
+    want = mo.features_quantiles(x, off)
+    B = off.size - 1
+    f, w = feat.reshape(B, G, 18), want.reshape(B, G, 18)
+    assert np.all(np.isnan(f[1]))
+    f, w = np.delete(f, 1, axis=0), np.delete(w, 1, axis=0)
+    np.testing.assert_array_equal(f[:, :, 2:], w[:, :, 2:])
+    np.testing.assert_allclose(f[:, :, :2], w[:, :, :2], rtol=3e-7, atol=3e-7)
+
+
 def test_targets_parity(torch_cuda):
     from paper_2401_10068_amd.cavi import cavi_warm_targets
 

@@ -215,3 +215,35 @@ def test_adamw_first_step_closed_form():
     w, g = np.array([1.0, -2.0, 0.5]), np.array([0.3, -4.0, 1e-3])
     w1, _, _ = mo.adamw(w, g, np.zeros(3), np.zeros(3), 1, 0.1, 0.9, 0.999, 1e-8, 0.01)
     np.testing.assert_allclose(w1, w - 0.1 * (np.sign(g) * np.abs(g) / (np.abs(g) + 1e-8) + 0.01 * w), rtol=1e-12)
+
+
+def test_quantile_features_are_order_statistics_by_counting():
+    """Each quantile feature is the value v with #{x < v} <= floor((j + 0.5) N / 16) < #{x <= v}
+    (checked by counting, not sorting), with ties, a ragged batch and a one-row dataset."""
+    rng = np.random.default_rng(3)
+    Ns = [1, 16, 17, 1000, 333]
+    x = np.round(rng.normal(25, 4, size=(sum(Ns), 5)), 1).astype(np.float32)  # many ties
+    off = np.concatenate([[0], np.cumsum(Ns)])
+    f = mo.features_quantiles(x, off)
+    base = mo.features(x, off)
+    for b, N in enumerate(Ns):
+        fb = f[b].reshape(5, 18)
+        assert np.array_equal(fb[:, :2], base[b].reshape(5, 18)[:, :2])  # moments as in features
+        rows = x[off[b]:off[b + 1]].astype(np.float64)
+        for g in range(5):
+            for j in range(16):
+                v = float(np.float32(fb[g, 2 + j] * 10.0 + 25.0))
+                r = int(np.floor((j + 0.5) / 16 * N))
+                cand = rows[:, g][np.abs(rows[:, g] - v) < 1e-4]
+                assert cand.size > 0
+                v = float(cand[0])
+                assert np.sum(rows[:, g] < v) <= r < np.sum(rows[:, g] <= v), (b, g, j)
+
+
+def test_quantile_features_of_a_known_sequence():
+    """Values 0..N-1 in a shuffled column: quantile j is floor((j + 0.5) N / 16)."""
+    N = 160
+    x = np.random.default_rng(4).permutation(N).astype(np.float32)[:, None]
+    f = mo.features_quantiles(x, [0, N])[0].reshape(1, 18)
+    want = (np.floor((np.arange(16) + 0.5) * N / 16) - 25.0) / 10.0
+    np.testing.assert_allclose(f[0, 2:], want, rtol=0, atol=1e-6)
