@@ -283,7 +283,14 @@ def linmix_dataset(seed: int, V: int, K_true, rho: float = 100.0, Lam=None, bloc
         z = np.empty((hi - lo, 2 * npair))
         z[:, 0::2] = rad * np.cos(th)
         z[:, 1::2] = rad * np.sin(th)
-        beta = K_true[None, :] + z[:, :M] @ L.T
+        # beta = K + L z, written out elementwise (no BLAS call, so no worker threads run while the
+        # inputs are generated)
+        beta = np.empty((hi - lo, M))
+        for i in range(M):
+            acc = np.zeros(hi - lo)
+            for jj in range(i + 1):
+                acc = acc + z[:, jj] * L[i, jj]
+            beta[:, i] = K_true[i] + acc
         w = philox4x32_10(glo, ghi, 0, STREAM_LM_NOISE, k0, k1)
         eps = np.sqrt(-2.0 * np.log(u53(w[0], w[1]))) * np.cos(2.0 * np.pi * u53(w[2], w[3]))
         mu = dd[:, -1]
