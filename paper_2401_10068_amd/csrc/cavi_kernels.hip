@@ -281,11 +281,17 @@ __global__ void k_list_all(Shape s, Bufs bf)
     if (i < s.nchunk) bf.act_chunk[i] = i;
 }
 
-// The datasets that will sweep again and their chunks, in ascending order (one workgroup: each
-// thread takes a contiguous range of datasets; exclusive scans of their counts give the offsets).
+// The datasets that will sweep again and their chunks, in ascending order (one workgroup): each
+// thread takes a contiguous range of datasets, exclusive scans of their counts give the offsets,
+// each thread leaves (list offset, first chunk, chunks) of its datasets in LDS by their place in
+// the list, then each wave writes whole datasets' chunk ranges (consecutive lanes, consecutive
+// entries).
+constexpr int kCompactMaxB = 4096;  // datasets whose list entries fit the workgroup's LDS
 __global__ __launch_bounds__(1024) void k_compact(Shape s, Bufs bf)
 {
     __shared__ int sd[1024], sc[1024];
+    __shared__ int l_off[kCompactMaxB], l_c0[kCompactMaxB], l_nc[kCompactMaxB];
+    if (s.B > kCompactMaxB) return;  // (not launched for such batches: their lists stay whole)
     const int t = threadIdx.x, per = (s.B + 1023) / 1024;
     const int b0 = min(s.B, t * per), b1 = min(s.B, b0 + per);
     int nd = 0, nc = 0;
@@ -307,12 +313,22 @@ __global__ __launch_bounds__(1024) void k_compact(Shape s, Bufs bf)
     int od = sd[t] - nd, oc = sc[t] - nc;
     for (int b = b0; b < b1; ++b)
         if (!sweep_skipped(bf.ctl + b)) {
-            bf.act_ds[od++] = b;
             const Ds d = bf.ds[b];
-            for (int c = 0; c < d.nchunk; ++c) bf.act_chunk[oc++] = d.chunk0 + c;
+            bf.act_ds[od] = b;
+            l_off[od] = oc;
+            l_c0[od] = d.chunk0;
+            l_nc[od] = d.nchunk;
+            ++od;
+            oc += d.nchunk;
         }
+    __syncthreads();
+    const int nds = sd[1023], lane = t & 63, wv = t >> 6;
+    for (int i = wv; i < nds; i += 16) {
+        const int o = l_off[i], c0 = l_c0[i], n = l_nc[i];
+        for (int c = lane; c < n; c += 64) bf.act_chunk[o + c] = c0 + c;
+    }
     if (t == 1023) {
-        bf.act_n[0] = sd[1023];
+        bf.act_n[0] = nds;
         bf.act_n[1] = sc[1023];
     }
 }
@@ -809,6 +825,7 @@ hipError_t launch_list_all(const Shape &s, const Bufs &b, hipStream_t st)
 
 hipError_t launch_compact(const Shape &s, const Bufs &b, hipStream_t st)
 {
+    if (s.B > kCompactMaxB) return hipSuccess;  // such a batch sweeps over its whole lists
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, st, s, b);
     return hipGetLastError();
 }

@@ -341,9 +341,13 @@ __device__ __forceinline__ void mstep_one(const Shape &s, const Bufs &bf, const 
 __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, int init_mode)
 {
     __shared__ MShared sh;
+    if (s.B == 1) {  // a single dataset: no work list
+        mstep_one(s, bf, p, init_mode, 0, sh);
+        return;
+    }
     const int nds = n_active_datasets(s, bf);
     for (int slot = blockIdx.x; slot < nds; slot += gridDim.x) {
-        mstep_one(s, bf, p, init_mode, active_dataset(s, bf, slot), sh);
+        mstep_one(s, bf, p, init_mode, bf.act_ds[slot], sh);
         __syncthreads();  // sh is rewritten by the next dataset
     }
 }

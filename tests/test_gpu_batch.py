@@ -130,3 +130,37 @@ def test_batch_run_matches_oracle_per_dataset(torch_cuda):
         eo = states[b].alpha / states[b].alpha.sum()
         np.testing.assert_allclose(ea, eo, atol=1e-4, rtol=0)
         assert abs(int(sw[b]) - n) <= max(3, 0.1 * n)
+
+
+@pytest.mark.parametrize("B", [700, 4200])
+def test_batch_run_work_lists_bitwise(torch_cuda, B):
+    """Runs to convergence in which datasets stop at different sweeps: with the work lists (the
+    datasets still sweeping and their chunks, rebuilt after every sweep) and, above 4,096 datasets,
+    without them (whole lists, finished datasets skipped chunk by chunk).  Every dataset's sweeps,
+    bound and state are bitwise those of a single handle run alone; datasets of 1 to 3 chunks."""
+    from paper_2401_10068_amd.cavi import CaviBatch
+
+    G = 16
+    rng = np.random.default_rng(B)
+    Ns = rng.integers(40, 5000, size=B)
+    Ks = rng.integers(2, 5, size=B).astype(np.int32)
+    x, row_off, *_ = synth.make_batch_gpu(77, Ns, Ks, synth.Recipe(K=4, G=G, mu_lo=15.0, mu_hi=19.0))
+    row_off = row_off.cpu().numpy()
+    bt = CaviBatch(x, Ns, Ks)
+    bt.init_standard(9)
+    sw, el, nconv = bt.run(300, 1e-6)
+    check = list(range(0, B, max(1, B // 12))) + [int(np.argmax(sw)), int(np.argmin(sw))]
+    got = {b: bt.get_state(b) for b in check}
+    bt.close()
+    assert len(set(sw.tolist())) > 3  # datasets stop at different sweeps
+    from paper_2401_10068_amd.cavi import Cavi
+
+    for b in check:
+        cx = Cavi(x[int(row_off[b]):int(row_off[b + 1])].contiguous(), int(Ks[b]))
+        cx.init_standard(9 + b)
+        n, L, conv = cx.run(300, 1e-6)
+        st = cx.get_state()
+        cx.close()
+        assert n == sw[b] and L == el[b], (b, n, sw[b], L, el[b])
+        for a, r in zip(got[b], st):
+            assert np.array_equal(a, r), b
