@@ -651,9 +651,10 @@ def batch_bench(args) -> int:
 
 def warm_bench(args) -> int:
     """Time to ELBO convergence (1e-6 relative) of 4,096 fresh K=8 datasets: plain GPU CAVI one
-    dataset at a time (sample), batched from the standard initialisation, and batched from the
-    learned warm start, for two feature sets side by side (per gene: moments and 16 nearest-rank
-    quantiles, the workload's definition; moments and 16 rank-bin means).  Plain CAVI is the
+    dataset at a time (sample), batched from the standard initialisation, and batched from a
+    learned warm start, three side by side: MLPs on per-dataset summary features (per gene:
+    moments and 16 nearest-rank quantiles, the workload's definition; moments and 16 rank-bin
+    means), and the learned refinement of the standard initialisation (RefineStart).  Plain CAVI is the
     judge: a warm-started dataset is accepted when its bound is within 1e-6 of the plain one (or
     better); the others fall back to plain CAVI, and the warm start's time to matching bounds is
     the warm batch (features + MLP + state + run) plus a batched plain run of the rejected
@@ -663,42 +664,54 @@ def warm_bench(args) -> int:
 
     from paper_2401_10068_amd import synth
     from paper_2401_10068_amd.cavi import Cavi, CaviBatch
-    from paper_2401_10068_amd.warmstart import WarmStart
+    from paper_2401_10068_amd.warmstart import RefineStart, WarmStart
 
     Ns, Ks, rec, seed = synth.batch_workload("c5eval")
     G, K = rec.G, int(Ks[0])
-    kinds = ["quantiles", "bins"] if args.features == "both" else [args.features]
-    nets = {}
+    kinds = ["quantiles", "bins", "refine", "refine@0.5"] if args.features == "all" else args.features.split(",")
+    nets, trained = {}, {}
     for kind in kinds:
-        ws = WarmStart(G=G, K=K, max_batch=1024, seed=args.mlp_seed, features=kind)
+        base, step = (kind.split("@")[0], float(kind.split("@")[1])) if "@" in kind else (kind, 1.0)
+        if base in trained:  # refine@s: the network trained for refine, another step along its move
+            nets[kind] = (trained[base][0], trained[base][1], step)
+            continue
+        if base == "refine":
+            ws = RefineStart(G=G, K=K, max_batch=1024, seed=args.mlp_seed)
+            n_train = args.refine_datasets
+        else:
+            ws = WarmStart(G=G, K=K, max_batch=1024, seed=args.mlp_seed, features=base)
+            n_train = args.train_datasets
         train = None
         if args.mlp_params:
-            ws.load(args.mlp_params.replace("{kind}", kind))
+            ws.load(args.mlp_params.replace("{kind}", base))
         else:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            losses = ws.train(args.train_datasets, batch=1024, lr=args.lr,
-                              log_every=max(1, args.train_datasets // 1024 // 10),
+            losses = ws.train(n_train, batch=1024, lr=args.lr,
+                              log_every=max(1, n_train // 1024 // 10),
                               log=lambda m, kind=kind: print(f"[{kind}] {m}", file=sys.stderr, flush=True))
             torch.cuda.synchronize()
-            train = {"datasets": args.train_datasets, "steps": int(losses.size), "batch": 1024,
+            train = {"datasets": n_train, "steps": int(losses.size), "batch": 1024,
                      "seconds": time.perf_counter() - t0, "loss_first": float(losses[0]),
                      "loss_last_avg10": float(losses[-10:].mean())}
             if args.save_mlp:
-                ws.save(args.save_mlp.replace("{kind}", kind))
-        nets[kind] = (ws, train)
+                ws.save(args.save_mlp.replace("{kind}", base))
+        trained[base] = (ws, train)
+        nets[kind] = (ws, train, step)
     x, row_off, _, _, _, _, _ = synth.make_batch_gpu(seed, Ns, Ks, rec)
     off_d = row_off.to(x.device)
     torch.cuda.synchronize()
 
-    def batched(ws, xb, Nb, Kb, offb, seed_b):
+    def batched(ws, xb, Nb, Kb, offb, seed_b, step=1.0):
         bt = CaviBatch(xb, Nb, Kb)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        if ws is not None:
-            ws.warm_start(bt, xb, offb)
-        else:
+        if ws is None:
             bt.init_standard(seed_b)
+        elif isinstance(ws, RefineStart):
+            ws.warm_start(bt, seed_b, step=step)  # the same standard initialisation, then the learned move
+        else:
+            ws.warm_start(bt, xb, offb)
         torch.cuda.synchronize()
         t_init = time.perf_counter() - t0
         sw, el, nconv = bt.run(args.max_sweeps, 1e-6)
@@ -712,8 +725,8 @@ def warm_bench(args) -> int:
     plain_b, psw, pel = batched(None, x, Ns, Ks, off_d, seed)
     tol = 1e-6 * np.abs(pel)
     results = {}
-    for kind, (ws, train) in nets.items():
-        warm_b, wsw, wel = batched(ws, x, Ns, Ks, off_d, seed)
+    for kind, (ws, train, step) in nets.items():
+        warm_b, wsw, wel = batched(ws, x, Ns, Ks, off_d, seed, step)
         accepted = wel >= pel - tol
         better = wel > pel + tol
         rej = np.flatnonzero(~accepted)
@@ -769,7 +782,7 @@ def warm_bench(args) -> int:
         "best_features": best,
         "speedup_batched_plain_vs_one_at_a_time": (t_plain / frac) / plain_b["total_s"],
     }
-    for ws, _ in nets.values():
+    for ws, _ in trained.values():
         ws.close()
     print(json.dumps(out), flush=True)
     return 0
@@ -797,8 +810,11 @@ def main() -> int:
     ap.add_argument("--mlp-params", default=None,
                     help="c5: load trained MLP parameters (.npy; '{kind}' in the path is replaced by the feature set)")
     ap.add_argument("--save-mlp", default=None, help="c5: save the trained parameters (.npy; '{kind}' as above)")
-    ap.add_argument("--features", default="both", choices=["both", "quantiles", "bins"],
-                    help="c5: warm-start feature sets to train and compare")
+    ap.add_argument("--features", default="all",
+                    help="c5: warm starts to train and compare: 'all' or a comma list of quantiles, bins, refine "
+                         "(refine@s: the learned move scaled by s)")
+    ap.add_argument("--refine-datasets", type=int, default=300_000,
+                    help="c5: generated datasets (run to convergence) the refinement is trained on")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library runs on one GPU; the sweep "

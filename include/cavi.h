@@ -191,6 +191,17 @@ cavi_status cavi_batch_set_state(cavi_batch *bt, int32_t b, const double *alpha,
  * stream. */
 cavi_status cavi_batch_set_state_warm(cavi_batch *bt, const float *out_dev, int32_t ld);
 
+/* Every dataset's current state as a row (rows_dev: caller device FP32, row
+ * b at rows_dev + b*ld) in the layout cavi_batch_set_state_warm reads back:
+ * (m - 25)/10 [K*G] | ln(a/b) [K*G] | ln max(alpha - alpha0, 1/2) [K]
+ * (alpha - alpha0 are the subpopulation counts N_k, floored at half a row;
+ * the softmax of their logs is N_k / N up to the floor), then, when
+ * with_centre != 0, the prior centre (m0 - 25)/10 [G].
+ * The learned refinement of the standard initialisation reads these rows.
+ * Synchronises.  CAVI_E_INVAL for NULL pointers or ld too small; CAVI_E_STATE
+ * without a state. */
+cavi_status cavi_batch_get_rows(cavi_batch *bt, float *rows_dev, int32_t ld, int32_t with_centre);
+
 cavi_status cavi_batch_get_state(cavi_batch *bt, int32_t b, double *alpha, double *m, double *beta,
                                  double *a, double *bb);
 
@@ -262,6 +273,13 @@ cavi_status cavi_features_quantiles(const float *x_dev, const int64_t *row_off_d
                                     float *feat_dev, void *hip_stream);
 cavi_status cavi_warm_targets(const double *pi_dev, const double *mu_dev, const double *tau_dev,
                               int32_t B, int32_t K, int32_t G, float *target_dev, void *hip_stream);
+/* y[i*ldy + j] += alpha * x[i*ldx + j] for i < n, j < m (device FP32 arrays,
+ * caller-owned; enqueued on hip_stream).  The refinement's targets (converged
+ * rows minus initial rows) and its output (initial rows plus the network's
+ * move) are formed with it.  CAVI_E_INVAL for NULL pointers, n or m < 1, or
+ * strides below m. */
+cavi_status cavi_rows_axpy(int32_t n, int32_t m, float alpha, const float *x_dev, int32_t ldx, float *y_dev,
+                           int32_t ldy, void *hip_stream);
 
 typedef struct cavi_mlp cavi_mlp;
 

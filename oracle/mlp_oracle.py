@@ -18,7 +18,9 @@ path computes so that the GPU kernels can be checked element by element:
 * ``init_params``  the SplitMix64 uniform initialisation;
 * ``warm_state``   the conversion of one output row into a variational state
   (conjugate posterior given the predicted moments; Dirichlet and
-  Normal-Gamma forms of eqs 16, 17 and 24).
+  Normal-Gamma forms of eqs 16, 17 and 24);
+* ``state_row``    the converse: a state as a row of that layout (the input and
+  the targets of the learned refinement of the standard initialisation).
 
 Pins: tests/test_mlp_oracle_pins.py.
 """
@@ -135,6 +137,17 @@ def warm_state(row, N: int, K: int, G: int, alpha0: float, beta0: float, a0: flo
     lt = np.clip(row[K * G:2 * K * G].reshape(K, G), -30.0, 30.0)
     b = a / np.exp(lt)
     return alpha, m, beta, a, b
+
+
+def state_row(alpha, m, a, b, alpha0: float, m0=None) -> np.ndarray:
+    """One state as a float32 row of the layout ``warm_state`` reads: (m - 25)/10 [K G] |
+    ln(a / b) [K G] | ln max(alpha - alpha0, 1/2) [K] (the counts N_k floored at half a row; their
+    softmax is N_k / N up to the floor), then, when m0 is given, (m0 - 25)/10 [G]."""
+    alpha, m, a, b = (np.asarray(v, dtype=np.float64) for v in (alpha, m, a, b))
+    parts = [((m - CENTRE) / SCALE).ravel(), np.log(a / b).ravel(), np.log(np.maximum(alpha - alpha0, 0.5))]
+    if m0 is not None:
+        parts.append((np.asarray(m0, dtype=np.float64) - CENTRE) / SCALE)
+    return np.concatenate(parts).astype(np.float32)
 
 
 # ----------------------------------------------------------------------------- MLP

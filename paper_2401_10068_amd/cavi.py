@@ -70,6 +70,8 @@ def lib():
             "cavi_batch_run": (st, [vp, C.c_int32, C.c_double, vp, vp, C.POINTER(C.c_int32)]),
             "cavi_batch_destroy": (st, [vp]),
             "cavi_batch_set_state_warm": (st, [vp, vp, C.c_int32]),
+            "cavi_batch_get_rows": (st, [vp, vp, C.c_int32, C.c_int32]),
+            "cavi_rows_axpy": (st, [C.c_int32, C.c_int32, C.c_float, vp, C.c_int32, vp, C.c_int32, vp]),
             "cavi_get_schedule": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
             "cavi_set_schedule": (st, [vp, C.c_int32]),
             "cavi_batch_get_schedule": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
@@ -381,6 +383,20 @@ class CaviBatch:
         _check(lib().cavi_batch_set_state_warm(self.h, C.c_void_p(out.data_ptr()),
                                                int(out.shape[1] if ld is None else ld)))
 
+    def get_rows(self, rows=None, with_centre: bool = False):
+        """Every dataset's state as a row of the warm-start layout (B x K(2G+1) float32, device;
+        with_centre: G more columns, the prior centre).  Writes into ``rows`` when given (its row
+        stride is its second dimension)."""
+        import torch
+
+        width = int(self.K.max()) * (2 * self.G + 1) + (self.G if with_centre else 0)
+        if rows is None:
+            rows = torch.empty((self.B, width), dtype=torch.float32, device=self.x.device)
+        _check_dev(rows, "rows", 2)
+        _check(lib().cavi_batch_get_rows(self.h, C.c_void_p(rows.data_ptr()), int(rows.shape[1]),
+                                         1 if with_centre else 0))
+        return rows
+
     def sweep(self, n: int):
         _check(lib().cavi_batch_sweep(self.h, int(n)))
 
@@ -440,6 +456,18 @@ def cavi_features(x, row_off, stream=None, kind: str = "bins"):
     _check(fn(C.c_void_p(x.data_ptr()), C.c_void_p(row_off.data_ptr()), B, G, C.c_void_p(feat.data_ptr()),
               _stream_ptr(stream)))
     return feat
+
+
+def cavi_rows_axpy(x, y, alpha: float = 1.0, cols: int | None = None, stream=None):
+    """y[:, :cols] += alpha x[:, :cols] (device float32 matrices with at least ``cols`` columns;
+    the row strides are their second dimensions)."""
+    _check_dev(x, "x", 2)
+    _check_dev(y, "y", 2)
+    n = min(x.shape[0], y.shape[0])
+    m = int(min(x.shape[1], y.shape[1]) if cols is None else cols)
+    _check(lib().cavi_rows_axpy(int(n), m, float(alpha), C.c_void_p(x.data_ptr()), int(x.shape[1]),
+                                C.c_void_p(y.data_ptr()), int(y.shape[1]), _stream_ptr(stream)))
+    return y
 
 
 def cavi_warm_targets(pi, mu, tau, stream=None):

@@ -740,6 +740,20 @@ cavi_status cavi_batch_set_state_warm(cavi_batch *bt, const float *out_dev, int3
     return CAVI_OK;
 }
 
+cavi_status cavi_batch_get_rows(cavi_batch *bt, float *rows_dev, int32_t ld, int32_t with_centre)
+{
+    if (!bt || !rows_dev) return fail(CAVI_E_INVAL, "NULL argument");
+    Handle *h = &bt->h;
+    if (!all_have_state(h)) return fail(CAVI_E_STATE, "no state: call init_standard or set_state");
+    for (int i = 0; i < h->s.B; ++i) {
+        const int64_t need = (int64_t)h->ds[i].K * (2 * h->s.G + 1) + (with_centre ? h->s.G : 0);
+        if (ld < need) return fail(CAVI_E_INVAL, "ld=%d < %lld (dataset %d)", ld, (long long)need, i);
+    }
+    HIPCHK(launch_state_rows(h->s, h->b, h->p, rows_dev, ld, with_centre ? 1 : 0, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return CAVI_OK;
+}
+
 cavi_status cavi_batch_get_state(cavi_batch *bt, int32_t b, double *alpha, double *m, double *beta, double *a,
                                  double *bb)
 {

@@ -172,5 +172,8 @@ hipError_t launch_mse(int n, float scale, const float *Y, const float *T, float 
 hipError_t launch_adamw(int64_t n, float *w, const float *g, float *m, float *v, float lr, float b1, float b2,
                         float eps, float wd, float c1, float c2, hipStream_t st);
 hipError_t launch_warm_state(const Shape &s, const Bufs &b, const Prior &p, const float *out, int ld, hipStream_t st);
+hipError_t launch_state_rows(const Shape &s, const Bufs &b, const Prior &p, float *rows, int ld, int centre,
+                             hipStream_t st);
+hipError_t launch_rows_axpy(int n, int m, float alpha, const float *x, int ldx, float *y, int ldy, hipStream_t st);
 
 }  // namespace cavi

@@ -451,7 +451,51 @@ __global__ void k_warm_state(Shape s, Bufs bf, Prior p, const float *__restrict_
     }
 }
 
+// Each dataset's state as a row of the warm-start layout that k_warm_state reads back: (m - 25) / 10
+// [K G] | ln(a / b) [K G] | ln max(alpha - alpha0, 1/2) [K] (the counts N_k, floored at half a row
+// so that an emptied subpopulation does not dominate a regression on these rows; their softmax is
+// E[pi]), then, with centre, (m0_g - 25) / 10 [G].  One workgroup per dataset.
+__global__ void k_state_rows(Shape s, Bufs bf, Prior p, float *__restrict__ rows, int ld, int centre)
+{
+    const int bi = blockIdx.x, tid = threadIdx.x, G = s.G;
+    const int K = bf.ds[bi].K;
+    float *o = rows + (size_t)bi * ld;
+    const size_t kb = (size_t)bi * s.Kmax, kg = kb * G;
+    for (int q = tid; q < K * G; q += kBlock) {
+        o[q] = (float)((bf.m[kg + q] - 25.0) / 10.0);
+        o[K * G + q] = (float)log(bf.a[kg + q] / bf.b[kg + q]);
+    }
+    if (tid < K) o[2 * K * G + tid] = (float)log(fmax(bf.alpha[kb + tid] - p.alpha0, 0.5));
+    if (centre)
+        for (int g = tid; g < G; g += kBlock) o[K * (2 * G + 1) + g] = (float)((bf.m0[(size_t)bi * G + g] - 25.0) / 10.0);
+}
+
+// y[i][j] += alpha x[i][j] for i < n, j < m (row strides ldx, ldy)
+__global__ void k_rows_axpy(int n, int m, float alpha, const float *__restrict__ x, int ldx, float *__restrict__ y,
+                            int ldy)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)n * m) return;
+    const int i = (int)(t / m), j = (int)(t - (int64_t)i * m);
+    y[(size_t)i * ldy + j] = fmaf(alpha, x[(size_t)i * ldx + j], y[(size_t)i * ldy + j]);
+}
+
 // ---------------------------------------------------------------------------------------------
+hipError_t launch_state_rows(const Shape &s, const Bufs &b, const Prior &p, float *rows, int ld, int centre,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_state_rows, dim3(s.B), dim3(kBlock), 0, st, s, b, p, rows, ld, centre);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_axpy(int n, int m, float alpha, const float *x, int ldx, float *y, int ldy, hipStream_t st)
+{
+    const int64_t tot = (int64_t)n * m;
+    hipLaunchKernelGGL(k_rows_axpy, dim3((unsigned)((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, n, m, alpha,
+                       x, ldx, y, ldy);
+    return hipGetLastError();
+}
+
 hipError_t launch_features(const float *x, const int64_t *row_off, int B, int G, float *feat, hipStream_t st)
 {
     hipLaunchKernelGGL(k_features, dim3(B), dim3(kBlock), 0, st, x, row_off, G, feat);

@@ -79,6 +79,15 @@ cavi_status cavi_features_quantiles(const float *x_dev, const int64_t *row_off_d
     return CAVI_OK;
 }
 
+cavi_status cavi_rows_axpy(int32_t n, int32_t m, float alpha, const float *x_dev, int32_t ldx, float *y_dev,
+                           int32_t ldy, void *hip_stream)
+{
+    if (!x_dev || !y_dev) return wfail(CAVI_E_INVAL, "NULL argument");
+    if (n < 1 || m < 1 || ldx < m || ldy < m) return wfail(CAVI_E_INVAL, "n=%d, m=%d, ldx=%d, ldy=%d", n, m, ldx, ldy);
+    WCHK(launch_rows_axpy(n, m, alpha, x_dev, ldx, y_dev, ldy, (hipStream_t)hip_stream));
+    return CAVI_OK;
+}
+
 cavi_status cavi_warm_targets(const double *pi_dev, const double *mu_dev, const double *tau_dev, int32_t B,
                               int32_t K, int32_t G, float *target_dev, void *hip_stream)
 {

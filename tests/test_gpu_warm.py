@@ -172,6 +172,39 @@ def test_quantile_features_parity(torch_cuda, G):
     np.testing.assert_allclose(f[:, :, :2], w[:, :, :2], rtol=3e-7, atol=3e-7)
 
 
+def test_state_rows_parity_and_axpy(torch_cuda):
+    """cavi_batch_get_rows writes each dataset's state as the oracle's state_row does (FP32
+    values from FP64 expressions: within one FP32 rounding), with and without the centre columns,
+    into a wider matrix (row stride); cavi_rows_axpy adds a scaled block of columns exactly as
+    FP32 fused multiply-adds do."""
+    from paper_2401_10068_amd.cavi import CaviBatch, cavi_rows_axpy
+
+    K, G = 8, 48
+    Ns = [700, 2100, 5000, 999]
+    x, off, *_ = cpu_batch(44, Ns, K, G)
+    bt = CaviBatch(torch_cuda.from_numpy(x).cuda(), Ns, [K] * len(Ns))
+    bt.init_standard(3)
+    bt.sweep(2)
+    W = K * (2 * G + 1)
+    wide = torch_cuda.full((len(Ns), W + G + 5), 7.0, dtype=torch_cuda.float32, device="cuda")
+    rows = bt.get_rows(wide, with_centre=True).cpu().numpy()
+    plain = bt.get_rows().cpu().numpy()
+    pr = oc.Prior()
+    for b in range(len(Ns)):
+        alpha, m, beta, a, bb = bt.get_state(b)
+        m0 = oc.data_mean(x[off[b]:off[b + 1]])
+        want = mo.state_row(alpha, m, a, bb, pr.alpha0, m0)
+        np.testing.assert_allclose(rows[b, :W + G], want, rtol=2.5e-7, atol=0)
+        assert np.all(rows[b, W + G:] == 7.0)  # nothing written past the row
+        np.testing.assert_array_equal(plain[b], rows[b, :W])
+    y = torch_cuda.from_numpy(plain.copy()).cuda()
+    cavi_rows_axpy(wide, y, -0.5, cols=W)
+    torch_cuda.cuda.synchronize()
+    want = (plain.astype(np.float64) - 0.5 * rows[:, :W].astype(np.float64)).astype(np.float32)
+    np.testing.assert_array_equal(y.cpu().numpy(), want)
+    bt.close()
+
+
 def test_targets_parity(torch_cuda):
     from paper_2401_10068_amd.cavi import cavi_warm_targets
 

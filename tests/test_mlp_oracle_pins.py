@@ -247,3 +247,28 @@ def test_quantile_features_of_a_known_sequence():
     f = mo.features_quantiles(x, [0, N])[0].reshape(1, 18)
     want = (np.floor((np.arange(16) + 0.5) * N / 16) - 25.0) / 10.0
     np.testing.assert_allclose(f[0, 2:], want, rtol=0, atol=1e-6)
+
+
+def test_state_row_round_trip_through_warm_state():
+    """A state after an update (alpha = alpha0 + N_k, beta = beta0 + N_k, a = a0 + N_k / 2) as a row
+    and back through warm_state is the same state (to float32 rounding of the row), including an
+    empty subpopulation; the centre columns follow."""
+    rng = np.random.default_rng(8)
+    K, G, N = 4, 6, 1000
+    alpha0, beta0, a0 = 1.0, 1e-3, 0.5
+    nk = np.array([400.0, 350.0, 249.75, 0.25])  # the last below the half-row floor
+    m = rng.uniform(15, 35, size=(K, G))
+    a = np.repeat((a0 + 0.5 * nk)[:, None], G, axis=1)
+    b = a / rng.gamma(2.0, 2.0, size=(K, G))
+    alpha = alpha0 + nk
+    m0 = rng.uniform(20, 30, size=G)
+    row = mo.state_row(alpha, m, a, b, alpha0, m0)
+    assert row.shape == (K * (2 * G + 1) + G,)
+    np.testing.assert_allclose(row[-G:], (m0 - 25) / 10, rtol=1e-6)
+    al, mm, be, aa, bb = mo.warm_state(row[:-G], N, K, G, alpha0, beta0, a0)
+    # the floor moves a quarter row into the last subpopulation: counts within 0.25 / N relative
+    np.testing.assert_allclose(al[:3], alpha[:3], rtol=3e-4)
+    assert abs((al[3] - alpha0) - 0.5 * N / (N + 0.25)) < 1e-3
+    np.testing.assert_allclose(mm, m, rtol=1e-6)
+    np.testing.assert_allclose(aa[:3], a[:3], rtol=3e-4)
+    np.testing.assert_allclose(bb[:3] / aa[:3], b[:3] / a[:3], rtol=3e-6)  # E[tau] kept
