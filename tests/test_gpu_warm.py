@@ -374,53 +374,53 @@ def test_warm_run_matches_oracle_and_plain(torch_cuda):
     assert accepted >= len(Ns) - 1, (el, pel)
 
 
-def test_trained_network_gains_over_untrained(torch_cuda):
-    """What training buys, measured on fresh datasets: the trained network's regression loss
-    is far below the untrained one's (it learns the targets' location and scale), and the
-    batched CAVI run from its warm start converges to bounds no worse on average than from the
-    untrained network's.  (Which optima the warm starts reach, against the standard
-    initialisation, is what bench.py --workload c5 reports.)"""
-    from paper_2401_10068_amd.cavi import CaviBatch, cavi_features, cavi_warm_targets
-    from paper_2401_10068_amd.warmstart import WarmStart
+def test_warm_starts_against_plain_cavi(torch_cuda):
+    """The learned warm starts against plain CAVI from the standard initialisation on a fixed
+    held-out set (192 fresh K=8, G=48 datasets, N log-uniform in [500, 4000], seed 49), every run
+    to a relative change of 1e-6.  A warm-started dataset is accepted when its converged bound is
+    at least the plain one - 1e-6 of it.  Measured with these training sizes: the refinement of
+    the standard initialisation is accepted on most datasets and needs about the sweeps of plain
+    CAVI; the rank-bin network is accepted on a few, where it needs far fewer sweeps.  The
+    thresholds sit below the measured values with room for the training's rounding."""
+    from paper_2401_10068_amd.cavi import CaviBatch
+    from paper_2401_10068_amd.warmstart import RefineStart, WarmStart
 
-    K, G, B = 8, 48, 96
+    K, G, B = 8, 48, 192
     rec = synth.Recipe(K=K, G=G, dir_alpha=1.0)
-    Ns, _ = synth.batch_shapes(46, B, 500, 4000, K, K)
+    Ns, _ = synth.batch_shapes(49, B, 500, 4000, K, K)
     Ks = np.full(B, K, dtype=np.int32)
-    x, row_off, _, pi, mu, tau, _ = synth.make_batch_gpu(46, Ns, Ks, rec)
+    x, row_off, *_ = synth.make_batch_gpu(49, Ns, Ks, rec)
     off_d = row_off.to(x.device)
-    feat = cavi_features(x, off_d)
-    tgt = cavi_warm_targets(pi, mu, tau)
 
-    def run(ws=None):
+    def run(start):
         bt = CaviBatch(x, Ns, Ks)
-        if ws is None:
-            bt.init_standard(7)
-        else:
-            ws.warm_start(bt, x, off_d)
+        start(bt)
         sw, el, nconv = bt.run(2000, 1e-6)
         bt.close()
+        assert nconv == B
         return sw, el
 
-    psw, pel = run()
-    untrained = WarmStart(G=G, K=K, max_batch=256, seed=11)
-    loss_u = untrained.mlp.loss_grad(feat, tgt)
-    usw, uel = run(untrained)
-    trained = WarmStart(G=G, K=K, max_batch=256, seed=11)
-    losses = trained.train(256 * 200, batch=256, lr=1e-3, warmup=20, n_lo=500, n_hi=4000, data_seed=47)
-    loss_t = trained.mlp.loss_grad(feat, tgt)
-    tsw, tel = run(trained)
-    scale = np.abs(pel)
-    gain = (tel - uel) / scale
-    acc_t = int(np.sum(tel >= pel - 1e-6 * scale))
-    acc_u = int(np.sum(uel >= pel - 1e-6 * scale))
-    print(f"held-out loss untrained {loss_u:.3f}, trained {loss_t:.3f}; mean bound gain {gain.mean():.4f}; "
-          f"accepted trained {acc_t}/{B}, untrained {acc_u}/{B}; sweeps median plain {np.median(psw)}, "
-          f"untrained {np.median(usw)}, trained {np.median(tsw)}")
-    assert np.all(np.isfinite(losses)) and loss_t < 0.6 * loss_u
-    assert gain.mean() > -0.01
-    untrained.close()
-    trained.close()
+    psw, pel = run(lambda bt: bt.init_standard(7))
+    tol = 1e-6 * np.abs(pel)
+    refine = RefineStart(G=G, K=K, max_batch=1024, seed=13)
+    rl = refine.train(1024 * 48, batch=1024, lr=1e-3, warmup=8, n_lo=500, n_hi=4000, data_seed=50)
+    rsw, rel = run(lambda bt: refine.warm_start(bt, 7))
+    bins = WarmStart(G=G, K=K, max_batch=1024, seed=13)
+    bl = bins.train(1024 * 48, batch=1024, lr=1e-3, warmup=8, n_lo=500, n_hi=4000, data_seed=50)
+    bsw, bel = run(lambda bt: bins.warm_start(bt, x, off_d))
+    refine.close()
+    bins.close()
+    acc_r, acc_b = rel >= pel - tol, bel >= pel - tol
+    ratio_r = rsw[acc_r].sum() / psw[acc_r].sum()
+    ratio_b = bsw[acc_b].sum() / max(1, psw[acc_b].sum())
+    print(f"plain sweeps median {np.median(psw)}; refine: loss {rl[0]:.3f} -> {rl[-8:].mean():.3f}, accepted "
+          f"{acc_r.sum()}/{B}, sweeps on them {ratio_r:.3f} x plain; bins: loss {bl[0]:.3f} -> {bl[-8:].mean():.3f}, "
+          f"accepted {acc_b.sum()}/{B}, sweeps on them {ratio_b:.3f} x plain")
+    assert np.all(np.isfinite(rl)) and np.all(np.isfinite(bl))
+    assert rl[-8:].mean() < rl[:2].mean() and bl[-8:].mean() < 0.6 * bl[:2].mean()
+    assert acc_r.mean() >= 0.80, acc_r.mean()
+    assert ratio_r <= 1.3, ratio_r
+    assert acc_b.sum() >= 5 and ratio_b <= 0.6, (acc_b.sum(), ratio_b)
 
 
 def test_warm_start_reads_the_finished_network_output(torch_cuda):
