@@ -281,55 +281,110 @@ __global__ void k_list_all(Shape s, Bufs bf)
     if (i < s.nchunk) bf.act_chunk[i] = i;
 }
 
-// The datasets that will sweep again and their chunks, in ascending order (one workgroup): each
-// thread takes a contiguous range of datasets, exclusive scans of their counts give the offsets,
-// each thread leaves (list offset, first chunk, chunks) of its datasets in LDS by their place in
-// the list, then each wave writes whole datasets' chunk ranges (consecutive lanes, consecutive
-// entries).
-constexpr int kCompactMaxB = 4096;  // datasets whose list entries fit the workgroup's LDS
+// The datasets that will sweep again and their chunks, in ascending order (one workgroup).
+// (1) Every dataset's skip test and chunk range are read with independent, coalesced loads
+// (thread t takes datasets t, t + 1024, ...) into LDS; (2) each thread takes a contiguous range
+// of up to four datasets from LDS, and exclusive scans of their counts (within each wave by lane
+// shuffles, then over the 16 wave totals) give the offsets; (3) each thread leaves (list offset,
+// first chunk, chunks) of its datasets in LDS by their place in the list, then each wave writes
+// whole datasets' chunk ranges (consecutive lanes, consecutive entries).
+constexpr int kCompactMaxB = 4096;  // datasets whose entries fit the workgroup's LDS
+constexpr int kCompactPer = kCompactMaxB / 1024;
+
+// inclusive scan of v over the 64 lanes of a wave
+__device__ __forceinline__ int wave_incl_scan(int v, int lane)
+{
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(v, off, 64);
+        if (lane >= off) v += u;
+    }
+    return v;
+}
+
 __global__ __launch_bounds__(1024) void k_compact(Shape s, Bufs bf)
 {
-    __shared__ int sd[1024], sc[1024];
     __shared__ int l_off[kCompactMaxB], l_c0[kCompactMaxB], l_nc[kCompactMaxB];
+    __shared__ int wd[16], wc[16], total;
     if (s.B > kCompactMaxB) return;  // (not launched for such batches: their lists stay whole)
-    const int t = threadIdx.x, per = (s.B + 1023) / 1024;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    // (1) by dataset index: first chunk, and chunks or -1 when the dataset will not sweep
+    {
+        bool act[kCompactPer];
+        Ds d[kCompactPer];
+#pragma unroll
+        for (int i = 0; i < kCompactPer; ++i) {
+            const int b = t + 1024 * i;
+            act[i] = false;
+            if (b < s.B) {
+                act[i] = !sweep_skipped(bf.ctl + b);
+                d[i] = bf.ds[b];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kCompactPer; ++i) {
+            const int b = t + 1024 * i;
+            if (b < s.B) {
+                l_c0[b] = d[i].chunk0;
+                l_nc[b] = act[i] ? d[i].nchunk : -1;
+            }
+        }
+    }
+    __syncthreads();
+    // (2) this thread's contiguous range of datasets
+    const int per = (s.B + 1023) / 1024;
     const int b0 = min(s.B, t * per), b1 = min(s.B, b0 + per);
-    int nd = 0, nc = 0;
-    for (int b = b0; b < b1; ++b)
-        if (!sweep_skipped(bf.ctl + b)) {
+    int c0[kCompactPer], nc[kCompactPer];
+    int nd = 0, ncs = 0;
+#pragma unroll
+    for (int i = 0; i < kCompactPer; ++i) {
+        const int b = b0 + i;
+        c0[i] = 0;
+        nc[i] = -1;
+        if (b < b1) {
+            c0[i] = l_c0[b];
+            nc[i] = l_nc[b];
+        }
+        if (nc[i] >= 0) {
             ++nd;
-            nc += bf.ds[b].nchunk;
+            ncs += nc[i];
         }
-    sd[t] = nd;
-    sc[t] = nc;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {  // inclusive scans (Hillis-Steele)
-        const int ad = t >= off ? sd[t - off] : 0, ac = t >= off ? sc[t - off] : 0;
-        __syncthreads();
-        sd[t] += ad;
-        sc[t] += ac;
-        __syncthreads();
     }
-    int od = sd[t] - nd, oc = sc[t] - nc;
-    for (int b = b0; b < b1; ++b)
-        if (!sweep_skipped(bf.ctl + b)) {
-            const Ds d = bf.ds[b];
-            bf.act_ds[od] = b;
+    const int id = wave_incl_scan(nd, lane), ic = wave_incl_scan(ncs, lane);
+    if (lane == 63) {
+        wd[wv] = id;
+        wc[wv] = ic;
+    }
+    __syncthreads();  // also ends every read of step (1)'s entries
+    if (t < 64) {
+        const int vd = lane < 16 ? wd[lane] : 0, vc = lane < 16 ? wc[lane] : 0;
+        const int sd = wave_incl_scan(vd, lane), sc = wave_incl_scan(vc, lane);
+        if (lane < 16) {
+            wd[lane] = sd - vd;  // exclusive offsets of the waves
+            wc[lane] = sc - vc;
+        }
+        if (lane == 15) {
+            total = sd;
+            bf.act_n[0] = sd;
+            bf.act_n[1] = sc;
+        }
+    }
+    __syncthreads();
+    int od = wd[wv] + id - nd, oc = wc[wv] + ic - ncs;
+#pragma unroll
+    for (int i = 0; i < kCompactPer; ++i)
+        if (nc[i] >= 0) {
+            bf.act_ds[od] = b0 + i;
             l_off[od] = oc;
-            l_c0[od] = d.chunk0;
-            l_nc[od] = d.nchunk;
+            l_c0[od] = c0[i];
+            l_nc[od] = nc[i];
             ++od;
-            oc += d.nchunk;
+            oc += nc[i];
         }
     __syncthreads();
-    const int nds = sd[1023], lane = t & 63, wv = t >> 6;
-    for (int i = wv; i < nds; i += 16) {
-        const int o = l_off[i], c0 = l_c0[i], n = l_nc[i];
-        for (int c = lane; c < n; c += 64) bf.act_chunk[o + c] = c0 + c;
-    }
-    if (t == 1023) {
-        bf.act_n[0] = nds;
-        bf.act_n[1] = sc[1023];
+    for (int i = wv; i < total; i += 16) {
+        const int o = l_off[i], c = l_c0[i], n = l_nc[i];
+        for (int k = lane; k < n; k += 64) bf.act_chunk[o + k] = c + k;
     }
 }
 
@@ -346,6 +401,91 @@ __global__ __launch_bounds__(kBlock) void k_colpart(Shape s, Bufs bf)
         double acc = 0.0;
         for (int64_t r = r0; r < r1; ++r) acc += (double)bf.x[r * G + g];
         bf.colpart[(size_t)chunk * G + g] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Passes that read every row of a chunk once (prior centre, k-means++ distances), for G a
+// multiple of 4 up to 128: each wave copies RW consecutive rows (contiguous in memory) with
+// 16-byte coalesced loads into an LDS slab of its own, of row stride G + 1 (odd, so that a lane
+// per row walking its genes and a lane per gene walking the rows both read without bank
+// conflicts).  The arithmetic and its order are those of the generic kernels.
+template <int G>
+struct Slab {
+    static constexpr int RW = G <= 64 ? 64 : 32;  // rows per wave slab
+    static constexpr int XS = G + 1;              // LDS row stride
+    static constexpr int C4 = G / 4;              // 16-byte pieces per row
+    static constexpr int PER = (RW * C4 + 63) / 64;
+    static_assert(G % 4 == 0 && G <= 128, "staged passes: G a multiple of 4, at most 128");
+};
+
+// this wave's LDS operations complete (and none moved across by the compiler)
+__device__ __forceinline__ void wave_lds_fence()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int G>
+__device__ __forceinline__ void stage_slab(float *xw, const float *src, int nr, int lane)
+{
+    using S = Slab<G>;
+    const float4 *s4 = (const float4 *)src;
+    const int n4 = nr * S::C4;
+    float4 v[S::PER];
+#pragma unroll
+    for (int i = 0; i < S::PER; ++i) {
+        const int q = lane + 64 * i;
+        if (q < n4) v[i] = s4[q];
+    }
+#pragma unroll
+    for (int i = 0; i < S::PER; ++i) {
+        const int q = lane + 64 * i;
+        if (q < n4) {
+            const int r = q / S::C4, c = 4 * (q - r * S::C4);
+            float *p = xw + r * S::XS + c;
+            p[0] = v[i].x;
+            p[1] = v[i].y;
+            p[2] = v[i].z;
+            p[3] = v[i].w;
+        }
+    }
+    wave_lds_fence();
+}
+
+// k_colpart with one wave per chunk (four chunks per workgroup): lane g sums gene g (and
+// g + 64) over the chunk's rows in row order
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_colpart_t(Shape s, Bufs bf)
+{
+    using S = Slab<G>;
+    constexpr int GL = (G + 63) / 64;  // genes per lane
+    __shared__ float xs[4][S::RW * S::XS];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int chunk = blockIdx.x * 4 + w;
+    if (chunk >= s.nchunk) return;  // per wave; no workgroup barrier follows
+    const Ds d = bf.ds[bf.chunk_ds[chunk]];
+    const int64_t cr = (int64_t)(chunk - d.chunk0) * kChunkRows;
+    const int nrc = (int)min((int64_t)kChunkRows, (int64_t)d.N - cr);
+    float *xw = xs[w];
+    double acc[GL];
+#pragma unroll
+    for (int i = 0; i < GL; ++i) acc[i] = 0.0;
+    for (int r0 = 0; r0 < nrc; r0 += S::RW) {
+        const int nr = min(S::RW, nrc - r0);
+        stage_slab<G>(xw, bf.x + (d.row0 + cr + r0) * G, nr, lane);
+        for (int r = 0; r < nr; ++r)
+#pragma unroll
+            for (int i = 0; i < GL; ++i) {
+                const int g = lane + 64 * i;
+                if (g < G) acc[i] += (double)xw[r * S::XS + g];
+            }
+        wave_lds_fence();  // the slab is read before the next one overwrites it
+    }
+#pragma unroll
+    for (int i = 0; i < GL; ++i) {
+        const int g = lane + 64 * i;
+        if (g < G) bf.colpart[(size_t)chunk * G + g] = acc[i];
     }
 }
 
@@ -464,6 +604,54 @@ __global__ __launch_bounds__(kBlock) void k_pp_d2(Shape s, Bufs bf, int j)
         __syncthreads();
     }
     if (tid == 0) bf.blockmax[chunk] = red[0];
+}
+
+// k_pp_d2 for G a multiple of 4 up to 128: each wave stages its own slabs of the chunk, a lane
+// per row
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_pp_d2_t(Shape s, Bufs bf, int j)
+{
+    using S = Slab<G>;
+    __shared__ float xs[4][S::RW * S::XS];
+    __shared__ double sd[G];
+    __shared__ double red[4];
+    const int chunk = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int bi = bf.chunk_ds[chunk];
+    const Ds d = bf.ds[bi];
+    if (j >= d.K) return;
+    const int64_t row = (int64_t)pp_state(s, bf, bi)[1];
+    const float *seed = bf.x + (d.row0 + row) * G;
+    if (chunk == d.chunk0)
+        for (int g = tid; g < G; g += kBlock) bf.seeds[((size_t)bi * s.Kmax + j) * G + g] = seed[g];
+    for (int g = tid; g < G; g += kBlock) sd[g] = (double)seed[g];
+    __syncthreads();
+    const int64_t cr = (int64_t)(chunk - d.chunk0) * kChunkRows;
+    const int nrc = (int)min((int64_t)kChunkRows, (int64_t)d.N - cr);
+    float *xw = xs[w];
+    double mx = 0.0;
+    for (int r0 = w * S::RW; r0 < nrc; r0 += 4 * S::RW) {
+        const int nr = min(S::RW, nrc - r0);
+        stage_slab<G>(xw, bf.x + (d.row0 + cr + r0) * G, nr, lane);
+        if (lane < nr) {
+#pragma clang fp contract(off)
+            const float *xr = xw + lane * S::XS;
+            double acc = 0.0;
+            for (int g = 0; g < G; ++g) {
+                const double dd = (double)xr[g] - sd[g];
+                acc = acc + dd * dd;
+            }
+            double *m = bf.mind2 + d.row0 + cr + r0 + lane;
+            const double v = j == 0 ? acc : fmin(*m, acc);
+            *m = v;
+            mx = fmax(mx, v);
+        }
+        wave_lds_fence();  // the slab is read before the next one overwrites it
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if (lane == 0) red[w] = mx;
+    __syncthreads();
+    if (tid == 0) bf.blockmax[chunk] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
 // one wave per dataset: e from the largest minD2 of its chunks
@@ -768,7 +956,16 @@ hipError_t launch_estep_stats(const Shape &s, const Bufs &b, int init_mode, hipS
 
 hipError_t launch_prior_mean(const Shape &s, const Bufs &b, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_colpart, dim3(s.nchunk), dim3(kBlock), 0, st, s, b);
+    const dim3 g4((s.nchunk + 3) / 4);
+    switch (s.G) {
+    case 16: hipLaunchKernelGGL(k_colpart_t<16>, g4, dim3(kBlock), 0, st, s, b); break;
+    case 32: hipLaunchKernelGGL(k_colpart_t<32>, g4, dim3(kBlock), 0, st, s, b); break;
+    case 48: hipLaunchKernelGGL(k_colpart_t<48>, g4, dim3(kBlock), 0, st, s, b); break;
+    case 64: hipLaunchKernelGGL(k_colpart_t<64>, g4, dim3(kBlock), 0, st, s, b); break;
+    case 96: hipLaunchKernelGGL(k_colpart_t<96>, g4, dim3(kBlock), 0, st, s, b); break;
+    case 128: hipLaunchKernelGGL(k_colpart_t<128>, g4, dim3(kBlock), 0, st, s, b); break;
+    default: hipLaunchKernelGGL(k_colpart, dim3(s.nchunk), dim3(kBlock), 0, st, s, b); break;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_colmean, dim3(s.B), dim3(kBlock), 0, st, s, b);
@@ -784,7 +981,16 @@ hipError_t launch_kmeanspp(const Shape &s, const Bufs &b, unsigned long long see
             hipLaunchKernelGGL(k_pp_wsum, dim3(s.nchunk), dim3(kBlock), 0, st, s, b, j);
             hipLaunchKernelGGL(k_pp_draw, dim3(s.B), dim3(64), 0, st, s, b, j);
         }
-        hipLaunchKernelGGL(k_pp_d2, dim3(s.nchunk), dim3(kBlock), 0, st, s, b, j);
+        const dim3 gc(s.nchunk), bk(kBlock);
+        switch (s.G) {
+        case 16: hipLaunchKernelGGL(k_pp_d2_t<16>, gc, bk, 0, st, s, b, j); break;
+        case 32: hipLaunchKernelGGL(k_pp_d2_t<32>, gc, bk, 0, st, s, b, j); break;
+        case 48: hipLaunchKernelGGL(k_pp_d2_t<48>, gc, bk, 0, st, s, b, j); break;
+        case 64: hipLaunchKernelGGL(k_pp_d2_t<64>, gc, bk, 0, st, s, b, j); break;
+        case 96: hipLaunchKernelGGL(k_pp_d2_t<96>, gc, bk, 0, st, s, b, j); break;
+        case 128: hipLaunchKernelGGL(k_pp_d2_t<128>, gc, bk, 0, st, s, b, j); break;
+        default: hipLaunchKernelGGL(k_pp_d2, gc, bk, 0, st, s, b, j); break;
+        }
     }
     return hipGetLastError();
 }

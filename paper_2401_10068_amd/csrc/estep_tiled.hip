@@ -127,6 +127,55 @@ __device__ __forceinline__ uint64_t clear_bit(uint64_t m, int j)
     return m;
 }
 
+// Statistics of Q rows taken in increasing order from the row mask m (which holds at least Q;
+// they are cleared from it): u1 += w d, u2 += w d^2 with d = x - centre, row after row, and
+// w = 1 without a multiplication when ONE.  All Q LDS reads are issued before the first use.
+template <int Q, int GS, int XS, bool ONE, typename WF>
+__device__ __forceinline__ void add_rows(uint64_t &m, const float *xl, const float (&mfv)[GS], float (&u1)[GS],
+                                         float (&u2)[GS], WF weight)
+{
+    int jr[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        jr[q] = __builtin_ctzll(m);
+        m = clear_bit(m, jr[q]);
+    }
+    float xq[Q][GS], wq[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        read_genes<GS>(xq[q], xl + jr[q] * XS);
+        wq[q] = ONE ? 1.f : weight(jr[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int sl = 0; sl < GS; ++sl) {
+            const float d = xq[q][sl] - mfv[sl];
+            if (ONE) {
+                u1[sl] += d;
+                u2[sl] = fmaf(d, d, u2[sl]);
+            } else {
+                const float wv = wq[q] * d;
+                u1[sl] += wv;
+                u2[sl] = fmaf(wv, d, u2[sl]);
+            }
+        }
+}
+
+// every row of the mask m, four at a time, then two, then one
+template <int GS, int XS, bool ONE, typename WF>
+__device__ __forceinline__ void add_all_rows(uint64_t m, const float *xl, const float (&mfv)[GS], float (&u1)[GS],
+                                             float (&u2)[GS], WF weight)
+{
+    int n = __builtin_popcountll(m);
+    for (; n >= 4; n -= 4) add_rows<4, GS, XS, ONE>(m, xl, mfv, u1, u2, weight);
+    if (n >= 2) {
+        add_rows<2, GS, XS, ONE>(m, xl, mfv, u1, u2, weight);
+        n -= 2;
+    }
+    if (n) add_rows<1, GS, XS, ONE>(m, xl, mfv, u1, u2, weight);
+}
+
 // sum over N genes from g0 of (h x + q)^2, x from an LDS row, (h, q) from an LDS table row;
 // UNROLL: all loads issued up front (more registers) or one block of 4 genes at a time
 template <int N, bool UNROLL>
@@ -383,18 +432,28 @@ __global__ __launch_bounds__(kBlock, (SCHED == 1 ? Cfg<KT, G>::LDS_WAVES : 2)) v
             for (int k = 0; k < KT; ++k) rv[k] = 0.f;
             if (INIT) {
                 // hard nearest seed by the FP64 squared distance, genes added in order, ties to
-                // the lowest seed (one lane per row)
-                if (act && half == 0) {
+                // the lowest seed.  The row's two lanes share the seeds: half 0 the even ones
+                // (seed 0 taken unconditionally, as the first of the sequence), half 1 the odd
+                // ones (taken only when strictly nearer than everything before, so a NaN distance
+                // never wins); then the nearer of the two, ties to the lower index, and seed 0
+                // whenever its distance is NaN.  This is the first minimum of the sequential
+                // scan over all seeds.
+                int best = half == 0 ? 0 : -1;
+                double bd = half == 0 ? 0.0 : INFINITY;
+                if (act) {
                     const float *xr0 = xs + j * XS;
-                    int best = 0;
-                    double bd = 0.0;
-                    for (int q = 0; q < K; ++q) {
+                    for (int q = half; q < K; q += 2) {
                         const double d2 = sqdist_lds(xr0, pt + q * PS, G);
                         if (q == 0 || d2 < bd) {
                             bd = d2;
                             best = q;
                         }
                     }
+                }
+                const double obd = __shfl_xor(bd, 32, 64);
+                const int obest = __shfl_xor(best, 32, 64);
+                if (act && half == 0) {
+                    if (bd == bd && obest >= 0 && (obd < bd || (obd == bd && obest < best))) best = obest;
 #pragma unroll
                     for (int k = 0; k < KT; ++k)
                         if (k == best) t0[k] += 1.f;
@@ -640,11 +699,10 @@ __global__ __launch_bounds__(kBlock, (SCHED == 1 ? Cfg<KT, G>::LDS_WAVES : 2)) v
             }  // phases A, B and log-sum-exp
 
             // C. statistics over the same rows, lanes over genes.  For each subpopulation
-            //    walk the rows whose responsibility for it is nonzero, two rows per step so
-            //    that their LDS reads overlap (a step without a second row adds the first
-            //    again with weight 0, which leaves the sums unchanged for finite data); rows
-            //    with a single responsibility of exactly 1 skip the multiplication.  Rows are added in increasing order (one-hot rows
-            //    first).  With KT = 16 the subpopulation loop is not unrolled, so the sums
+            //    walk the rows whose responsibility for it is nonzero, four rows per step so
+            //    that their LDS reads overlap; rows with a single responsibility of exactly 1
+            //    skip the multiplication.  Rows are added one after another in increasing
+            //    order (one-hot rows first).  With KT = 16 the subpopulation loop is not unrolled, so the sums
             //    cannot be indexed statically: the slab's rows are summed in two registers
             //    and that sum is added to the wave's running sum; otherwise the rows are
             //    added to the running sum directly.
@@ -663,8 +721,8 @@ __global__ __launch_bounds__(kBlock, (SCHED == 1 ? Cfg<KT, G>::LDS_WAVES : 2)) v
                     if (k >= K) break;
                     const uint64_t rows = __ballot((mk >> k) & 1u);
                     if (!rows) continue;
-                    uint64_t one = rows & hard;
-                    uint64_t soft = rows & ~hard;
+                    const uint64_t one = rows & hard;
+                    const uint64_t soft = rows & ~hard;
                     float mfv[GS], u1[GS], u2[GS];
 #pragma unroll
                     for (int sl = 0; sl < GS; ++sl) {
@@ -677,58 +735,14 @@ __global__ __launch_bounds__(kBlock, (SCHED == 1 ? Cfg<KT, G>::LDS_WAVES : 2)) v
 #pragma unroll
                         for (int sl = 0; sl < GS; ++sl) mfv[sl] = mfr[k][sl];
                     }
-                    while (one) {
-                        const int ja = __builtin_ctzll(one);
-                        one = clear_bit(one, ja);
-                        const bool two = one != 0;
-                        const int jb = two ? __builtin_ctzll(one) : ja;
-                        one = clear_bit(one, jb);  // no-op when it was the last row
-                        // without a second row, row ja enters again with weight 0
-                        const float w = two ? 1.f : 0.f;
-                        float xa[GS], xb[GS];
-                        read_genes<GS>(xa, xl + ja * XS);
-                        read_genes<GS>(xb, xl + jb * XS);
-#pragma unroll
-                        for (int sl = 0; sl < GS; ++sl) {
-                            const float d = xa[sl] - mfv[sl];
-                            u1[sl] += d;
-                            u2[sl] = fmaf(d, d, u2[sl]);
-                        }
-#pragma unroll
-                        for (int sl = 0; sl < GS; ++sl) {
-                            const float d = xb[sl] - mfv[sl];
-                            u1[sl] = fmaf(d, w, u1[sl]);
-                            u2[sl] = fmaf(d * w, d, u2[sl]);
-                        }
-                    }
-                    while (soft) {
-                        const int ja = __builtin_ctzll(soft);
-                        soft = clear_bit(soft, ja);
-                        const bool two = soft != 0;
-                        const int jb = two ? __builtin_ctzll(soft) : ja;
-                        soft = clear_bit(soft, jb);  // no-op when it was the last row
-                        const float ra = LOWREG ? ls[(jbase + ja) * LS + k]
-                                                : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rv[k]), ja));
-                        const float rb0 = LOWREG ? ls[(jbase + jb) * LS + k]
-                                                 : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rv[k]), jb));
-                        const float rb = two ? rb0 : 0.f;
-                        float xa[GS], xb[GS];
-                        read_genes<GS>(xa, xl + ja * XS);
-                        read_genes<GS>(xb, xl + jb * XS);
-#pragma unroll
-                        for (int sl = 0; sl < GS; ++sl) {
-                            const float d = xa[sl] - mfv[sl];
-                            const float wv = ra * d;
-                            u1[sl] += wv;
-                            u2[sl] = fmaf(wv, d, u2[sl]);
-                        }
-#pragma unroll
-                        for (int sl = 0; sl < GS; ++sl) {
-                            const float d = xb[sl] - mfv[sl];
-                            const float wv = rb * d;
-                            u1[sl] += wv;
-                            u2[sl] = fmaf(wv, d, u2[sl]);
-                        }
+                    const auto unit = [](int) { return 1.f; };
+                    add_all_rows<GS, XS, true>(one, xl, mfv, u1, u2, unit);
+                    if (soft) {
+                        const auto resp = [&](int jj) {
+                            return LOWREG ? ls[(jbase + jj) * LS + k]
+                                          : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rv[k]), jj));
+                        };
+                        add_all_rows<GS, XS, false>(soft, xl, mfv, u1, u2, resp);
                     }
 #pragma unroll
                     for (int sl = 0; sl < GS; ++sl) {

@@ -132,12 +132,15 @@ def test_batch_run_matches_oracle_per_dataset(torch_cuda):
         assert abs(int(sw[b]) - n) <= max(3, 0.1 * n)
 
 
-@pytest.mark.parametrize("B", [700, 4200])
+@pytest.mark.parametrize("B", [700, 3500, 4200])
 def test_batch_run_work_lists_bitwise(torch_cuda, B):
     """Runs to convergence in which datasets stop at different sweeps: with the work lists (the
-    datasets still sweeping and their chunks, rebuilt after every sweep) and, above 4,096 datasets,
-    without them (whole lists, finished datasets skipped chunk by chunk).  Every dataset's sweeps,
-    bound and state are bitwise those of a single handle run alone; datasets of 1 to 3 chunks."""
+    datasets still sweeping and their chunks, rebuilt after every sweep; 700 datasets: one per
+    thread of the list builder, 3,500: four) and, above 4,096 datasets, without them (whole lists,
+    finished datasets skipped chunk by chunk).  With the lists, every dataset's sweeps and bound
+    are bitwise those of a single handle run alone (a dataset missing from a list for one sweep
+    would lag), and so are the states of a sample; without them, the sample's.  Datasets of 1 to
+    3 chunks."""
     from paper_2401_10068_amd.cavi import CaviBatch
 
     G = 16
@@ -149,8 +152,9 @@ def test_batch_run_work_lists_bitwise(torch_cuda, B):
     bt = CaviBatch(x, Ns, Ks)
     bt.init_standard(9)
     sw, el, nconv = bt.run(300, 1e-6)
-    check = list(range(0, B, max(1, B // 12))) + [int(np.argmax(sw)), int(np.argmin(sw))]
-    got = {b: bt.get_state(b) for b in check}
+    sample = list(range(0, B, max(1, B // 12))) + [int(np.argmax(sw)), int(np.argmin(sw))]
+    check = range(B) if B <= 4096 else sample
+    got = {b: bt.get_state(b) for b in sample}
     bt.close()
     assert len(set(sw.tolist())) > 3  # datasets stop at different sweeps
     from paper_2401_10068_amd.cavi import Cavi
@@ -159,8 +163,9 @@ def test_batch_run_work_lists_bitwise(torch_cuda, B):
         cx = Cavi(x[int(row_off[b]):int(row_off[b + 1])].contiguous(), int(Ks[b]))
         cx.init_standard(9 + b)
         n, L, conv = cx.run(300, 1e-6)
-        st = cx.get_state()
+        st = cx.get_state() if b in got else None
         cx.close()
         assert n == sw[b] and L == el[b], (b, n, sw[b], L, el[b])
-        for a, r in zip(got[b], st):
-            assert np.array_equal(a, r), b
+        if st is not None:
+            for a, r in zip(got[b], st):
+                assert np.array_equal(a, r), b

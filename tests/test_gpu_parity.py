@@ -256,6 +256,51 @@ def test_default_prior_mean(torch_cuda):
     np.testing.assert_allclose(m0, X.astype(np.float64).mean(0), rtol=1e-12)
 
 
+@pytest.mark.parametrize("G", [16, 48, 96, 128, 33])
+def test_prior_mean_is_the_chunked_row_order_sum(torch_cuda, G):
+    """The default prior centre is defined as FP64 sums of each 2048-row chunk's rows in row order,
+    added in chunk order, over N.  Written out here with sequential accumulation (numpy's
+    add.accumulate, not a pairwise sum), it matches the device bitwise, for the staged passes (G a
+    multiple of 4 up to 128, whole chunks and a ragged last one) and the generic one (G = 33)."""
+    N = 2 * 2048 + 1234
+    X = overlapping(40 + G, N, 3, G)
+    from paper_2401_10068_amd.cavi import Cavi
+
+    cx = Cavi(to_dev(torch_cuda, X), 3)
+    m0 = cx.prior_mean()
+    cx.close()
+    X64 = X.astype(np.float64)
+    parts = [np.add.accumulate(X64[c:c + 2048], axis=0)[-1] for c in range(0, N, 2048)]
+    want = np.add.accumulate(np.stack(parts), axis=0)[-1] / N
+    assert np.array_equal(m0, want), np.max(np.abs(m0 - want))
+
+
+@pytest.mark.parametrize("G,K", [(32, 5), (64, 7), (128, 4), (20, 3)])
+def test_standard_init_matches_oracle_other_shapes(torch_cuda, G, K):
+    """k-means++ seeds (the D^2 pass staged per wave for G a multiple of 4 up to 128; generic
+    otherwise), the hard nearest-seed statistics (a row's two lanes share the seeds) and the
+    first update, against the oracle: three chunks with a ragged tail.  alpha, m, beta and a
+    within 1e-6; b within the one-update bar 1e-5 plus 1e-7 x T2 / (2 (b - b0)), the FP32
+    statistics' precision model with the statistics summed about the seed rows (measured: 1.3e-6
+    at G = 64, K = 7, from FP32 sums of up to 512 rows per wave)."""
+    N = 2 * 2048 + 777
+    X = overlapping(60 + G, N, K, G, lo=15.0, hi=25.0)
+    pr = oc.Prior()
+    m0 = oc.data_mean(X)
+    ost, seeds, r = oc.init_standard(X, K, pr, m0, seed=11, want_r=True)
+    cx = gpu_ctx(torch_cuda, X, K, m0)
+    cx.init_standard(11)
+    g = cx.get_state()
+    cx.close()
+    for name, gv, ov in zip(["alpha", "m", "beta", "a"], g[:4], ost.arrays()[:4]):
+        assert rel_err(gv, ov) <= 1e-6, (G, K, name)
+    c = X[seeds].astype(np.float64)
+    d = X.astype(np.float64)[:, None, :] - c[None]
+    factor = np.einsum("nk,nkg->kg", r, d * d) / (2.0 * (ost.b - pr.b0))
+    err = np.abs(g[4] - ost.b) / ost.b
+    assert np.all(err <= ONE_SWEEP_RTOL + 1e-7 * factor), float(np.max(err / (ONE_SWEEP_RTOL + 1e-7 * factor)))
+
+
 # --------------------------------------------------------------------------- errors
 def test_error_paths(torch_cuda):
     from paper_2401_10068_amd import cavi
