@@ -228,6 +228,18 @@ __device__ __forceinline__ void mstep_one(const Shape &s, const Bufs &bf, const 
     } else if (tid >= 128 && tid < 128 + K) {
         const int k = tid - 128;
         sh.lg_a[k] = dev_lgamma(p.a0 + 0.5 * total(v, k));
+    } else if ((tid >= 192 && tid < 256) || (!init_mode && tid >= 256 && tid < 320)) {
+        // digamma (wave 3) and lgamma (wave 4) of sum(alpha), whose terms are known already
+        double x = 0.0;
+        for (int k = tid & 63; k < K; k += 64) x += p.alpha0 + total(v, k);
+        x = wave_sum(x);
+        if (tid == 192) {
+            sh.asum = x;
+            sh.psum = dev_digamma(x);
+        }
+        if (tid == 256) sh.lg_asum = dev_lgamma(x);
+    } else if (!init_mode && tid == 320) {
+        sh.lg_prior = dev_lgamma(K * p.alpha0) - K * dev_lgamma(p.alpha0);
     }
     __syncthreads();
     const double half_ln_b0 = 0.5 * log(p.beta0 / kTwoPi);
@@ -271,20 +283,6 @@ __device__ __forceinline__ void mstep_one(const Shape &s, const Bufs &bf, const 
         if (!isfinite(mm) || !isfinite(bb) || !isfinite(elt) || !isfinite(T2q)) bad = 1;
     }
     if (bad) atomicOr(&sh.bad, 1);
-    __syncthreads();
-    // digamma and lgamma of sum(alpha) and the Dirichlet prior's normaliser, in different
-    // waves at the same time
-    if (tid < 64 || (!init_mode && tid < 128)) {
-        double x = 0.0;
-        for (int k = tid & 63; k < K; k += 64) x += sh.ak[k];
-        x = wave_sum(x);
-        if (tid == 0) {
-            sh.asum = x;
-            sh.psum = dev_digamma(x);
-        }
-        if (tid == 64) sh.lg_asum = dev_lgamma(x);
-    }
-    if (!init_mode && tid == 128) sh.lg_prior = dev_lgamma(K * p.alpha0) - K * dev_lgamma(p.alpha0);
     __syncthreads();
     coef_rows(v, sh, &p, !init_mode);
     {
