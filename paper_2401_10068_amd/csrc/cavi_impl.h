@@ -59,6 +59,10 @@ struct Ds {
     int32_t nchunk;   // chunks of this dataset
 };
 
+// nearest[] value of a row whose distance to seed 0 is NaN: the hard assignment takes seed 0
+// whatever the later distances (the first-minimum scan keeps its first element when that is NaN)
+constexpr uint8_t kNearestLocked = 255;
+
 struct Shape {
     int32_t B;          // datasets
     int32_t G;          // genes (shared)
@@ -94,6 +98,7 @@ struct Bufs {
     Ctl *ctl;             // B
     int32_t *count;       // 1: datasets still sweeping
     double *mind2;        // Ntot             (initialisation)
+    uint8_t *nearest;     // Ntot             (initialisation) nearest seed so far, kNearestLocked: seed 0
     double *blockmax;     // nchunk           (initialisation)
     unsigned long long *blocksum;  // nchunk  (initialisation)
     double *colpart;      // nchunk x G      (prior centre)

@@ -20,19 +20,6 @@ namespace {
 
 constexpr int kMaxItems = kMaxKG / kBlock;  // (k, g) items per thread
 
-// Squared distance in FP64 with separate multiply and add (no contraction),
-// so that the host reproduces it bit for bit.
-__device__ __forceinline__ double sqdist64(const float *x, const float *y, int G)
-{
-#pragma clang fp contract(off)
-    double s = 0.0;
-    for (int g = 0; g < G; ++g) {
-        double d = (double)x[g] - (double)y[g];
-        s = s + d * d;
-    }
-    return s;
-}
-
 template <int KT>
 __device__ __forceinline__ void row_loglik(const float *xr, int G, int K, const float2 *__restrict__ hq,
                                            const float *__restrict__ cc, float (&l)[KT])
@@ -115,7 +102,6 @@ __global__ __launch_bounds__(kBlock) void k_estep_stats(Shape s, Bufs bf, int in
         const float *cc = bf.cc + kb;
         const float2 *hq = (const float2 *)bf.hq + kb * G;
         const float *mf = bf.mf + kb * G;
-        const float *seeds = bf.seeds + kb * G;
         float mfv[kMaxItems];
 #pragma unroll
         for (int it = 0; it < kMaxItems; ++it) {
@@ -142,15 +128,8 @@ __global__ __launch_bounds__(kBlock) void k_estep_stats(Shape s, Bufs bf, int in
                 if (tid < nr) {
                     const float *xr = xs + tid * XS;
                     if (init_mode) {
-                        int best = 0;
-                        double bd = 0.0;
-                        for (int j = 0; j < K; ++j) {
-                            const double d2 = sqdist64(xr, seeds + j * G, G);
-                            if (j == 0 || d2 < bd) {
-                                bd = d2;
-                                best = j;
-                            }
-                        }
+                        const uint8_t nb = bf.nearest[t + tid];
+                        const int best = nb == kNearestLocked ? 0 : nb;
 #pragma unroll
                         for (int k = 0; k < KT; ++k) rrow[k] = (k == best) ? 1.f : 0.f;
                     } else {
@@ -550,6 +529,22 @@ __global__ void k_pp_begin(Shape s, Bufs bf, unsigned long long seed)
     st[0] = rng;
 }
 
+// The hard assignment's nearest seed, kept during the distance passes: the first minimum of the
+// sequential scan over the seeds (seed 0 taken first, a later seed only when strictly nearer
+// than every earlier one, so a NaN distance never replaces; a NaN distance to seed 0 keeps seed 0
+// whatever follows).  The distances are the passes' own FP64 values, genes added in order, so
+// this is the nearest seed by that definition.  `old` is the smallest distance of the earlier
+// seeds, as minD2 holds it (minD2 ignores NaN distances, as the scan does after seed 0).
+__device__ __forceinline__ void update_nearest(uint8_t *p, int j, double acc, double old)
+{
+    if (j == 0) {
+        *p = acc != acc ? kNearestLocked : 0;
+    } else {
+        const uint8_t o = *p;
+        if (o != kNearestLocked && acc < old) *p = (uint8_t)j;
+    }
+}
+
 // one workgroup per chunk: minD2 against seed j (rows staged through LDS 32 genes at a time),
 // the chunk maximum, and the copy of the seed row into the seed table
 __global__ __launch_bounds__(kBlock) void k_pp_d2(Shape s, Bufs bf, int j)
@@ -592,9 +587,11 @@ __global__ __launch_bounds__(kBlock) void k_pp_d2(Shape s, Bufs bf, int j)
         }
         if (tid < nr) {
             double *m = bf.mind2 + d.row0 + c0 + r0 + tid;
-            const double v = j == 0 ? acc : fmin(*m, acc);
+            const double old = j == 0 ? acc : *m;
+            const double v = j == 0 ? acc : fmin(old, acc);
             *m = v;
             mx = fmax(mx, v);
+            update_nearest(bf.nearest + d.row0 + c0 + r0 + tid, j, acc, old);
         }
     }
     red[tid] = mx;
@@ -641,9 +638,11 @@ __global__ __launch_bounds__(kBlock) void k_pp_d2_t(Shape s, Bufs bf, int j)
                 acc = acc + dd * dd;
             }
             double *m = bf.mind2 + d.row0 + cr + r0 + lane;
-            const double v = j == 0 ? acc : fmin(*m, acc);
+            const double old = j == 0 ? acc : *m;
+            const double v = j == 0 ? acc : fmin(old, acc);
             *m = v;
             mx = fmax(mx, v);
+            update_nearest(bf.nearest + d.row0 + cr + r0 + lane, j, acc, old);
         }
         wave_lds_fence();  // the slab is read before the next one overwrites it
     }
@@ -824,7 +823,7 @@ size_t workspace_bytes(const Shape &s)
     n += al(B * red_split_max(s.Nmax) * s.Smax * 8);  // totals
     n += al(B * s.hist_cap * 8);
     n += al(B * sizeof(Ctl)) + al(4);
-    n += al((size_t)s.Ntot * 8);
+    n += al((size_t)s.Ntot * 8) + al((size_t)s.Ntot);  // mind2, nearest
     n += 2 * al(nblk * 8);
     n += al((size_t)s.nchunk * G * 8);
     n += al(2 * 4) + al(B * 4) + al((size_t)s.nchunk * 4);  // work lists
@@ -864,6 +863,7 @@ void carve(const Shape &s, void *ws, Bufs &b)
     b.ctl = (Ctl *)take(B * sizeof(Ctl));
     b.count = (int32_t *)take(4);
     b.mind2 = (double *)take((size_t)s.Ntot * 8);
+    b.nearest = (uint8_t *)take((size_t)s.Ntot);
     b.blockmax = (double *)take(nblk * 8);
     b.blocksum = (unsigned long long *)take(nblk * 8);
     b.colpart = (double *)take((size_t)s.nchunk * G * 8);

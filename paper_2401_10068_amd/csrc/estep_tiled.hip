@@ -202,19 +202,6 @@ __device__ __forceinline__ float tail_sum(const float *xr, const float *pr, int 
     return s;
 }
 
-// FP64 squared distance of an LDS row to a seed stored at the even entries of a table row,
-// genes added in order (the definition of the initialisation's nearest seed)
-__device__ __forceinline__ double sqdist_lds(const float *x, const float *t, int G)
-{
-#pragma clang fp contract(off)
-    double s = 0.0;
-    for (int g = 0; g < G; ++g) {
-        const double d = (double)x[g] - (double)t[2 * g];
-        s = s + d * d;
-    }
-    return s;
-}
-
 // Workgroup barrier that waits only for this wave's LDS operations: the
 // prefetch of the next tile (global loads) stays in flight across it.
 __device__ __forceinline__ void lds_barrier()
@@ -431,29 +418,11 @@ __global__ __launch_bounds__(kBlock, (SCHED == 1 ? Cfg<KT, G>::LDS_WAVES : 2)) v
 #pragma unroll
             for (int k = 0; k < KT; ++k) rv[k] = 0.f;
             if (INIT) {
-                // hard nearest seed by the FP64 squared distance, genes added in order, ties to
-                // the lowest seed.  The row's two lanes share the seeds: half 0 the even ones
-                // (seed 0 taken unconditionally, as the first of the sequence), half 1 the odd
-                // ones (taken only when strictly nearer than everything before, so a NaN distance
-                // never wins); then the nearer of the two, ties to the lower index, and seed 0
-                // whenever its distance is NaN.  This is the first minimum of the sequential
-                // scan over all seeds.
-                int best = half == 0 ? 0 : -1;
-                double bd = half == 0 ? 0.0 : INFINITY;
-                if (act) {
-                    const float *xr0 = xs + j * XS;
-                    for (int q = half; q < K; q += 2) {
-                        const double d2 = sqdist_lds(xr0, pt + q * PS, G);
-                        if (q == 0 || d2 < bd) {
-                            bd = d2;
-                            best = q;
-                        }
-                    }
-                }
-                const double obd = __shfl_xor(bd, 32, 64);
-                const int obest = __shfl_xor(best, 32, 64);
+                // hard nearest seed, found by the k-means++ distance passes (FP64 squared
+                // distances, genes added in order, the first minimum over the seeds)
                 if (act && half == 0) {
-                    if (bd == bd && obest >= 0 && (obd < bd || (obd == bd && obest < best))) best = obest;
+                    const uint8_t nb = bf.nearest[r0 + (int64_t)t * kT + j];
+                    const int best = nb == kNearestLocked ? 0 : nb;
 #pragma unroll
                     for (int k = 0; k < KT; ++k)
                         if (k == best) t0[k] += 1.f;
