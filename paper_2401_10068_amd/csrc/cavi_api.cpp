@@ -429,7 +429,11 @@ cavi_status run_all(Handle *h, int32_t max_sweeps, double rel_tol)
     HIPCHK(launch_ctl_begin(h->s, h->b, max_sweeps, 1, rel_tol, 0, h->stream));
     HIPCHK(launch_list_all(h->s, h->b, h->stream));
     int issued = 0;
-    int batch = 1;  // graphs between host checks, doubled up to 8
+    // graphs between host checks: 1, then 2 (a check after 16 sweeps, then every 32).  Sweeps
+    // enqueued after the last dataset has converged only skip, but each still costs its four
+    // launches (about 19 us for a batch of 4,096 datasets): checking every 32 sweeps instead of
+    // every 128 took such a batch's run (200 to 200,000 rows, G = 48) from 55.3 to 53.9 ms
+    int batch = 1;
     for (;;) {
         for (int i = 0; i < batch && issued < max_sweeps; ++i) {
             rs = replay(h, kGraphSweeps);
@@ -440,7 +444,7 @@ cavi_status run_all(Handle *h, int32_t max_sweeps, double rel_tol)
         HIPCHK(hipMemcpyAsync(h->hcount, h->b.count, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
         if (*h->hcount == 0 || issued >= max_sweeps) break;
-        if (batch < 8) batch *= 2;
+        if (batch < 2) batch *= 2;
     }
     HIPCHK(hipMemcpyAsync(h->hctl, h->b.ctl, sizeof(Ctl) * h->s.B, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));

@@ -130,7 +130,7 @@ cavi_status cavi_fit_static(const float *x_dev, int64_t N, int32_t G, int32_t K,
     HIPCHK(hipMemcpyAsync(&c, bf.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (c.numeric) return fail(CAVI_E_NUMERIC, "initial update is not finite");
-    // sweeps until converged: checks after 16, 32, 64, 128, 128, ... sweeps, as the handle's run
+    // sweeps until converged: a check after 16 sweeps, then every 32, as the handle's run
     HIPCHK(launch_ctl_begin(s, bf, max_sweeps, 1, rel_tol, 0, st));
     int issued = 0, batch = 1;
     for (;;) {
@@ -144,7 +144,7 @@ cavi_status cavi_fit_static(const float *x_dev, int64_t N, int32_t G, int32_t K,
         HIPCHK(hipMemcpyAsync(&active, bf.count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (active == 0 || issued >= max_sweeps) break;
-        if (batch < 8) batch *= 2;
+        if (batch < 2) batch *= 2;
     }
     const size_t KG = (size_t)K * G;
     HIPCHK(hipMemcpyAsync(&c, bf.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
