@@ -132,7 +132,7 @@ __device__ __forceinline__ uint64_t clear_bit(uint64_t m, int j)
 // w = 1 without a multiplication when ONE.  All Q LDS reads are issued before the first use.
 template <int Q, int GS, int XS, bool ONE, typename WF>
 __device__ __forceinline__ void add_rows(uint64_t &m, const float *xl, const float (&mfv)[GS], float (&u1)[GS],
-                                         float (&u2)[GS], WF weight)
+                                         float (&u2)[GS], float &u0, WF weight)
 {
     int jr[Q];
 #pragma unroll
@@ -145,6 +145,10 @@ __device__ __forceinline__ void add_rows(uint64_t &m, const float *xl, const flo
     for (int q = 0; q < Q; ++q) {
         read_genes<GS>(xq[q], xl + jr[q] * XS);
         wq[q] = ONE ? 1.f : weight(jr[q]);
+    }
+    if (!ONE) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) u0 += wq[q];
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q)
@@ -165,15 +169,15 @@ __device__ __forceinline__ void add_rows(uint64_t &m, const float *xl, const flo
 // every row of the mask m, four at a time, then two, then one
 template <int GS, int XS, bool ONE, typename WF>
 __device__ __forceinline__ void add_all_rows(uint64_t m, const float *xl, const float (&mfv)[GS], float (&u1)[GS],
-                                             float (&u2)[GS], WF weight)
+                                             float (&u2)[GS], float &u0, WF weight)
 {
     int n = __builtin_popcountll(m);
-    for (; n >= 4; n -= 4) add_rows<4, GS, XS, ONE>(m, xl, mfv, u1, u2, weight);
+    for (; n >= 4; n -= 4) add_rows<4, GS, XS, ONE>(m, xl, mfv, u1, u2, u0, weight);
     if (n >= 2) {
-        add_rows<2, GS, XS, ONE>(m, xl, mfv, u1, u2, weight);
+        add_rows<2, GS, XS, ONE>(m, xl, mfv, u1, u2, u0, weight);
         n -= 2;
     }
-    if (n) add_rows<1, GS, XS, ONE>(m, xl, mfv, u1, u2, weight);
+    if (n) add_rows<1, GS, XS, ONE>(m, xl, mfv, u1, u2, u0, weight);
 }
 
 // sum over N genes from g0 of (h x + q)^2, x from an LDS row, (h, q) from an LDS table row;
@@ -389,10 +393,14 @@ __global__ __launch_bounds__(kBlock, (SCHED == 1 ? Cfg<KT, G>::LDS_WAVES : 2)) v
             e0k = kq < K ? 0x1p-14f * (fabsf(ccs[kq]) + sq + wk + 4.f * G) : 0.f;
         }
 
-        float t0[KT], t1[KT][GS], t2[KT][GS];
+        // t0n, t0: the wave's count of one-hot rows and sum of the other responsibilities of
+        // subpopulation `lane`, formed in the statistics walk (the soft sums per slab in FP32,
+        // then in FP64); t1, t2: the lane's genes' sums
+        uint32_t t0n = 0;
+        double t0 = 0.0;
+        float t1[KT][GS], t2[KT][GS];
 #pragma unroll
         for (int k = 0; k < KT; ++k) {
-            t0[k] = 0.f;
 #pragma unroll
             for (int sl = 0; sl < GS; ++sl) t1[k][sl] = t2[k][sl] = 0.f;
         }
@@ -423,9 +431,6 @@ __global__ __launch_bounds__(kBlock, (SCHED == 1 ? Cfg<KT, G>::LDS_WAVES : 2)) v
                 if (act && half == 0) {
                     const uint8_t nb = bf.nearest[r0 + (int64_t)t * kT + j];
                     const int best = nb == kNearestLocked ? 0 : nb;
-#pragma unroll
-                    for (int k = 0; k < KT; ++k)
-                        if (k == best) t0[k] += 1.f;
                     mk = (1u << best) | kOneHot;
                 }
             } else {
@@ -599,23 +604,69 @@ __global__ __launch_bounds__(kBlock, (SCHED == 1 ? Cfg<KT, G>::LDS_WAVES : 2)) v
             bool single = false;
             if constexpr (GB < G && KT <= 8) single = !__ballot(act && half == 0 && done != (1u << kone));
             if (single) {
+                // every row of the slab is one-hot (or has no finite term): the statistics walk
+                // needs no responsibilities, only the row masks
                 if (act && half == 0) {
                     const bool fin = isfinite(lone);
-                    const float r = fin ? 1.f : 0.f;
-#pragma unroll
-                    for (int k = 0; k < KT; ++k) {
-                        rv[k] = k == kone ? r : 0.f;
-                        t0[k] += rv[k];
-                    }
                     if (fin) mk |= (1u << kone) | kOneHot;
                     hacc += fin ? 0.0 : (double)__int_as_float(0x7fc00000);
-                    if (LOWREG) {
-                        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-                        for (int q = 0; q < KT; q += 4) *(f4 *)(lr + q) = f4{rv[q], rv[q + 1], rv[q + 2], rv[q + 3]};
-                    }
                 }
-            } else if (act && half == 0) {
+            } else if (KT > 8 && act) {
+                // the row's two lanes share the subpopulations: half h forms those of
+                // KT/2 h .. KT/2 h + KT/2 - 1 and the halves exchange maximum, sum, entropy,
+                // counts and masks; the responsibilities replace the row's l values in LDS
+                constexpr int KQ = KT / 2;
+                const int kb = half * KQ;
+                float l[KQ];
+#pragma unroll
+                for (int q = 0; q < KQ; q += 4) {
+                    const f4 a = *(const f4 *)(lr + kb + q);
+                    l[q] = a.x, l[q + 1] = a.y, l[q + 2] = a.z, l[q + 3] = a.w;
+                }
+                const uint32_t dh = done >> kb;
+#pragma unroll
+                for (int j = 0; j < KQ; ++j) l[j] = (dh & (1u << j)) ? l[j] : -INFINITY;
+                float mxh = l[0];
+#pragma unroll
+                for (int j = 1; j < KQ; ++j) mxh = fmaxf(mxh, l[j]);
+                const float mx = fmaxf(mxh, __shfl_xor(mxh, 32, 64));
+                float seh = 0.f;
+#pragma unroll
+                for (int j = 0; j < KQ; ++j) {
+                    const float e = __expf(l[j] - mx);
+                    seh += (dh & (1u << j)) ? e : 0.f;
+                }
+                const float se = seh + __shfl_xor(seh, 32, 64);
+                const float L = mx + __logf(se);
+                float hh = (half == 0 && !isfinite(L)) ? __int_as_float(0x7fc00000) : 0.f;
+                int nzh = 0;
+                uint32_t mkh = 0;
+                float rsum = 0.f, rq[KQ];
+#pragma unroll
+                for (int j = 0; j < KQ; ++j) {
+                    const float dl = l[j] - L;
+                    const bool take = (dh & (1u << j)) && dl > -kLogRCut;
+                    const float e = __expf(dl);
+                    rq[j] = take ? e : 0.f;
+                    hh = take ? hh - rq[j] * dl : hh;
+                    mkh |= rq[j] != 0.f ? 1u << (kb + j) : 0u;
+                    nzh += rq[j] != 0.f;
+                    rsum += rq[j];
+                }
+                const int nz = nzh + __shfl_xor(nzh, 32, 64);
+                // with a single nonzero term the sum is that term, whatever the order
+                const float rone = rsum + __shfl_xor(rsum, 32, 64);
+                const uint32_t mka = mkh | (uint32_t)__shfl_xor((int)mkh, 32, 64);
+                const float h = hh + __shfl_xor(hh, 32, 64);
+                if (half == 0) {
+                    mk |= mka;
+                    if (nz == 1 && rone == 1.f) mk |= kOneHot;
+                    hacc += (double)h;
+                }
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int q = 0; q < KQ; q += 4) *(f4 *)(lr + kb + q) = f4{rq[q], rq[q + 1], rq[q + 2], rq[q + 3]};
+            } else if (KT <= 8 && act && half == 0) {
                 // every term is formed and the computed set selects it (no branches); adding
                 // +0 for a term outside the set leaves a sum unchanged
                 float l[KT];
@@ -647,7 +698,6 @@ __global__ __launch_bounds__(kBlock, (SCHED == 1 ? Cfg<KT, G>::LDS_WAVES : 2)) v
                     h = take ? h - rv[k] * dl : h;
                     mk |= rv[k] != 0.f ? 1u << k : 0u;
                     nz += rv[k] != 0.f;
-                    t0[k] += rv[k];
                 }
                 if (nz == 1) {
                     float rone = 0.f;
@@ -663,7 +713,7 @@ __global__ __launch_bounds__(kBlock, (SCHED == 1 ? Cfg<KT, G>::LDS_WAVES : 2)) v
                     for (int q = 0; q < KT; q += 4) *(f4 *)(lr + q) = f4{rv[q], rv[q + 1], rv[q + 2], rv[q + 3]};
                 }
             }
-            if (LOWREG) wave_lds_sync();
+            if (LOWREG || KT > 8) wave_lds_sync();
 
             }  // phases A, B and log-sum-exp
 
@@ -704,14 +754,20 @@ __global__ __launch_bounds__(kBlock, (SCHED == 1 ? Cfg<KT, G>::LDS_WAVES : 2)) v
 #pragma unroll
                         for (int sl = 0; sl < GS; ++sl) mfv[sl] = mfr[k][sl];
                     }
+                    // counts: the one-hot rows (responsibility exactly 1), then the others' weights
+                    // in row order
+                    if (lane == k) t0n += (uint32_t)__builtin_popcountll(one);
+                    float u0 = 0.f;
                     const auto unit = [](int) { return 1.f; };
-                    add_all_rows<GS, XS, true>(one, xl, mfv, u1, u2, unit);
+                    add_all_rows<GS, XS, true>(one, xl, mfv, u1, u2, u0, unit);
                     if (soft) {
                         const auto resp = [&](int jj) {
-                            return LOWREG ? ls[(jbase + jj) * LS + k]
-                                          : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rv[k]), jj));
+                            return (LOWREG || KT > 8)
+                                       ? ls[(jbase + jj) * LS + k]
+                                       : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rv[k]), jj));
                         };
-                        add_all_rows<GS, XS, false>(soft, xl, mfv, u1, u2, resp);
+                        add_all_rows<GS, XS, false>(soft, xl, mfv, u1, u2, u0, resp);
+                        if (lane == k) t0 += (double)u0;
                     }
 #pragma unroll
                     for (int sl = 0; sl < GS; ++sl) {
@@ -730,9 +786,8 @@ __global__ __launch_bounds__(kBlock, (SCHED == 1 ? Cfg<KT, G>::LDS_WAVES : 2)) v
         double *wd = (double *)ls;   // 4 x KT counts, then 4 entropies
 #pragma unroll
         for (int k = 0; k < KT; ++k) {
-            const double c0 = wave_sum((double)t0[k]);
             if (k < K) {
-                if (lane == 0) wd[w * KT + k] = c0;
+                if (lane == k) wd[w * KT + k] = (double)t0n + t0;
                 if (gown) {
 #pragma unroll
                     for (int sl = 0; sl < GS; ++sl) {
