@@ -119,9 +119,17 @@ __device__ __forceinline__ int active_chunk(const Shape &s, const Bufs &b, int i
 __device__ __forceinline__ int n_active_datasets(const Shape &s, const Bufs &b) { return s.B == 1 ? 1 : min(s.B, b.act_n[0]); }
 __device__ __forceinline__ int active_dataset(const Shape &s, const Bufs &b, int i) { return s.B == 1 ? 0 : b.act_ds[i]; }
 
+// Record of dataset bi; a single-dataset handle's follows from the shape, without a load.
+__device__ __forceinline__ Ds dataset(const Shape &s, const Bufs &b, int bi)
+{
+    return s.B == 1 ? Ds{0, (int32_t)s.Ntot, s.Kmax, 0, s.nchunk} : b.ds[bi];
+}
+
 __device__ __forceinline__ bool sweep_skipped(const Ctl *c)
 {
-    return c->numeric || c->call_sweeps >= c->max_call || (c->stop_on_conv && c->converged);
+    // every field loaded (no short-circuit), so that the loads overlap
+    const int32_t cs = c->call_sweeps, mx = c->max_call, so = c->stop_on_conv, cv = c->converged, nu = c->numeric;
+    return (nu != 0) | (cs >= mx) | ((so != 0) & (cv != 0));
 }
 
 // Text returned by cavi_last_error() for the calling thread.

@@ -26,10 +26,12 @@ __device__ __forceinline__ double wave_sum(double v)
 
 struct MShared {
     double red[kMBlock / 64];
-    double ak[kMaxK], psi_ak[kMaxK], lg_ak[kMaxK], term_k[kMaxK], nk[kMaxK];
+    double ak[kMaxK], psi_ak[kMaxK], lg_ak[kMaxK], term_k[kMaxK];
     double psi_a[kMaxK], lg_a[kMaxK], ln_bt[kMaxK];  // per component: digamma, lgamma of a_kg; ln(beta_kg / 2 pi)
     double tmp[kMaxKG];
-    double asum, psum, lg_asum, lg_prior;
+    double psum, lg_asum;                 // digamma, lgamma of sum(alpha)
+    double lg_ka0, lg_alpha0, lg_a0;      // lgamma of K alpha0, alpha0, a0
+    double ln_b0pi, ln_b0;                // ln(beta0 / 2 pi), ln b0
     int bad;
 };
 
@@ -51,7 +53,8 @@ __device__ __forceinline__ View view(const Shape &s, const Bufs &bf, int bi)
 {
     View v;
     const size_t kb = (size_t)bi * s.Kmax, kg = kb * s.G;
-    v.K = bf.ds[bi].K;
+    const Ds d = dataset(s, bf, bi);
+    v.K = d.K;
     v.G = s.G;
     v.alpha = bf.alpha + kb;
     v.nalpha = bf.nalpha + kb;
@@ -69,38 +72,59 @@ __device__ __forceinline__ View view(const Shape &s, const Bufs &bf, int bi)
     v.mf = bf.mf + kg;
     v.totals = bf.totals + (size_t)bi * red_split_max(s.Nmax) * s.Smax;
     v.smax = (size_t)s.Smax;
-    v.nsplit = red_split(bf.ds[bi].nchunk);
+    v.nsplit = red_split(d.nchunk);
     v.hist = bf.hist + (size_t)bi * s.hist_cap;
     v.ctl = bf.ctl + bi;
     return v;
 }
 
-// Statistic i of the dataset: the sums of its chunk ranges, added in range order.
-__device__ __forceinline__ double total(const View &v, int i)
+// Statistic i of the dataset: the sums of its chunk ranges, added in range order.  The
+// kRedSplit loads are issued without a branch (a dataset of one range reads its single sum
+// kRedSplit times), so that the loads of several statistics can be in flight together.
+struct Tot {
+    double r[kRedSplit];
+};
+
+__device__ __forceinline__ Tot load_total(const View &v, int i)
 {
-    double t = v.totals[i];
-    if (v.nsplit > 1) {  // kRedSplit ranges: their loads issued together
+    const double *t = v.totals + i;
+    const size_t stride = v.nsplit > 1 ? v.smax : 0;
+    Tot o;
 #pragma unroll
-        for (int z = 1; z < kRedSplit; ++z) t += v.totals[z * v.smax + i];
-    }
-    return t;
+    for (int z = 0; z < kRedSplit; ++z) o.r[z] = t[z * stride];
+    return o;
 }
+
+__device__ __forceinline__ double sum_total(const View &v, const Tot &o)
+{
+    double sum = o.r[0];
+#pragma unroll
+    for (int z = 1; z < kRedSplit; ++z) sum += o.r[z];
+    return v.nsplit > 1 ? sum : o.r[0];
+}
+
+__device__ __forceinline__ double total(const View &v, int i) { return sum_total(v, load_total(v, i)); }
 
 // Per-(k,g) coefficients of the E-step from one subpopulation-gene state:
 //   l_nk = c_k - sum_g (h x + q)^2,  h = sqrt(E[tau]/2),  q = -m h,
 //   c_k  = E ln pi_k + sum_g tmp_kg,  tmp = (E ln tau - ln 2pi - 1/beta) / 2.
-__device__ __forceinline__ double coef_item(const View &v, int q, double mm, double bt, double aa, double bb,
-                                            double elt)
+__device__ __forceinline__ void coef_hq(const View &v, int q, double mm, double aa, double bb)
 {
     const float hf = (float)sqrt(0.5 * aa / bb);
     v.hq[2 * q] = hf;
     v.hq[2 * q + 1] = (float)(-mm * (double)hf);
     v.mf[q] = (float)mm;
+}
+
+__device__ __forceinline__ double coef_item(const View &v, int q, double mm, double bt, double aa, double bb,
+                                            double elt)
+{
+    coef_hq(v, q, mm, aa, bb);
     return 0.5 * (elt - kLn2Pi - 1.0 / bt);
 }
 
 // c_k from the per-(k,g) parts in LDS: wave w sums subpopulations w, w+16, ...
-__device__ __forceinline__ void coef_rows(const View &v, MShared &sh, const Prior *p, int with_bound)
+__device__ __forceinline__ void coef_rows(const View &v, MShared &sh)
 {
     const int G = v.G, K = v.K;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -113,10 +137,6 @@ __device__ __forceinline__ void coef_rows(const View &v, MShared &sh, const Prio
             const double c = elnpi + x;
             v.cc[k] = (float)c;
             if (!isfinite(c)) sh.bad = 1;
-            if (with_bound) {
-                const double ak = sh.ak[k];
-                sh.term_k[k] = sh.nk[k] * elnpi + (p->alpha0 - 1.0) * elnpi + sh.lg_ak[k] - (ak - 1.0) * elnpi;
-            }
         }
     }
 }
@@ -138,29 +158,39 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce(Shape s, Bufs bf, int init
     const int nds = n_active_datasets(s, bf);
     for (int slot = blockIdx.y; slot < nds; slot += gridDim.y) {
         const int bi = active_dataset(s, bf, slot);
-        if (!init_mode && sweep_skipped(bf.ctl + bi)) continue;
-        const Ds d = bf.ds[bi];
+        const Ds d = dataset(s, bf, bi);
         const int S = d.K + 2 * d.K * s.G + 1;
         if (blockIdx.x * 64 >= S) continue;
         const int Z = red_split(d.nchunk);
         if (z >= Z) continue;
-        const int r0 = (int)(((int64_t)d.nchunk * z) / Z), r1 = (int)(((int64_t)d.nchunk * (z + 1)) / Z);
-        const double *pp = bf.partials + (size_t)(d.chunk0 + r0) * s.Smax;
+        // 32-bit products: a dataset has fewer than 2^31 rows, so fewer than 2^20 chunks
+        const int r0 = (d.nchunk * z) / Z, r1 = (d.nchunk * (z + 1)) / Z;
         const int nr = r1 - r0;
-        double acc = 0.0;
-        if (i < S) {
-            const int c0 = (int)(((int64_t)nr * wv) / nw), c1 = (int)(((int64_t)nr * (wv + 1)) / nw);
-            double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
-            int c = c0;
-            for (; c + 4 <= c1; c += 4) {
-                q0 += pp[(size_t)c * s.Smax + i];
-                q1 += pp[(size_t)(c + 1) * s.Smax + i];
-                q2 += pp[(size_t)(c + 2) * s.Smax + i];
-                q3 += pp[(size_t)(c + 3) * s.Smax + i];
+        const int c0 = (nr * wv) / nw, c1 = (nr * (wv + 1)) / nw;
+        const int n = c1 - c0, n4 = n & ~3;  // this wave's chunks; those in whole groups of four
+        // lanes past the statistics read the last one (their sums are not stored)
+        const double *pp = bf.partials + (size_t)(d.chunk0 + r0 + c0) * s.Smax + min(i, S - 1);
+        // chunks in batches of eight loads in flight (indices clamped to the wave's last chunk);
+        // the first batch is requested before the skip test
+        double L[8];
+        auto load8 = [&](int b0) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) L[k] = pp[(size_t)min(b0 + k, n - 1) * s.Smax];
+        };
+        if (n > 0) load8(0);
+        if (!init_mode && sweep_skipped(bf.ctl + bi)) continue;
+        double q[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int b0 = 0; b0 < n; b0 += 8) {
+            if (b0 > 0) load8(b0);
+            // chunk t adds to accumulator t mod 4 while in a whole group of four, else to the first
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int t = b0 + k;
+                if (t < n4) q[k & 3] += L[k];
+                else if (t < n) q[0] += L[k];
             }
-            for (; c < c1; ++c) q0 += pp[(size_t)c * s.Smax + i];
-            acc = (q0 + q1) + (q2 + q3);
         }
+        const double acc = (q[0] + q[1]) + (q[2] + q[3]);
         part[wv][lane] = acc;
         __syncthreads();
         if (wv == 0 && i < S) {
@@ -192,7 +222,7 @@ __global__ __launch_bounds__(kMBlock) void k_coef(Shape s, Bufs bf)
         if (tid == 0) sh.psum = dev_digamma(x);
     }
     __syncthreads();
-    coef_rows(v, sh, nullptr, 0);
+    coef_rows(v, sh);
 }
 
 // Conjugate updates from the totals, written with sums around the E-step's
@@ -207,54 +237,121 @@ __device__ __forceinline__ void mstep_one(const Shape &s, const Bufs &bf, const 
 {
     const View v = view(s, bf, bi);
     Ctl *ctl = v.ctl;
-    if (!init_mode && sweep_skipped(ctl)) return;
     const int G = v.G, K = v.K, KG = K * G, tid = threadIdx.x;
+    const int lane = tid & 63, role = kMBlock / 64 - 1 - (tid >> 6);  // wave 15 - role
+    // Every statistic this thread reads is requested at once, before the skip test, so that one
+    // memory latency covers them all: its first item (q = tid; clamped indices where the thread
+    // has none), the count of its lane's subpopulation, the entropy.
+    const int q0 = tid, k0 = q0 / G;
+    const bool has0 = q0 < KG;
+    const int qc = has0 ? q0 : KG - 1, kc = qc / G;
+    const Tot lN = load_total(v, kc), lT1 = load_total(v, K + qc), lT2 = load_total(v, K + KG + qc);
+    const Tot lR = load_total(v, lane < K ? lane : 0), lH = load_total(v, K + 2 * KG);
+    const float c0 = v.mf[qc];
+    const double m00 = v.m0[qc - kc * G];
+    if (!init_mode && sweep_skipped(ctl)) return;
+    const double N0 = sum_total(v, lN), T10 = sum_total(v, lT1), T20 = sum_total(v, lT2);
+    const double nr = sum_total(v, lR), Hq = sum_total(v, lH);
     if (tid == 0) sh.bad = 0;
-    if (tid < K) {
-        const double nk = total(v, tid);
-        sh.nk[tid] = nk;
-        const double a = p.alpha0 + nk;
-        sh.ak[tid] = a;
-        sh.psi_ak[tid] = dev_digamma(a);
-        sh.lg_ak[tid] = dev_lgamma(a);
-        v.nalpha[tid] = a;
-    } else if (tid >= 64 && tid < 64 + K) {
-        // a_kg = a0 + N_k / 2 and beta_kg = beta0 + N_k are the same for every gene of a
-        // subpopulation: their special functions once per subpopulation, in other waves
-        const int k = tid - 64;
-        const double nk = total(v, k);
-        sh.psi_a[k] = dev_digamma(p.a0 + 0.5 * nk);
-        sh.ln_bt[k] = log((p.beta0 + nk) / kTwoPi);
-    } else if (tid >= 128 && tid < 128 + K) {
-        const int k = tid - 128;
-        sh.lg_a[k] = dev_lgamma(p.a0 + 0.5 * total(v, k));
-    } else if ((tid >= 192 && tid < 256) || (!init_mode && tid >= 256 && tid < 320)) {
-        // digamma (wave 3) and lgamma (wave 4) of sum(alpha), whose terms are known already
-        double x = 0.0;
-        for (int k = tid & 63; k < K; k += 64) x += p.alpha0 + total(v, k);
-        x = wave_sum(x);
-        if (tid == 192) {
-            sh.asum = x;
-            sh.psum = dev_digamma(x);
+
+    // Special functions, one function per wave and one argument per lane, in the top three waves
+    // (which hold no items while K G <= 832), while the item threads run the parts of their updates
+    // that do not need them.  Digamma (wave 15) and lgamma (wave 14) of alpha_k = alpha0 + N_k,
+    // of a_kg = a0 + N_k / 2 (the same for every gene of a subpopulation) and of sum(alpha); the
+    // lgamma wave adds K alpha0, alpha0 and a0.  Logarithms (wave 13) of beta_kg / 2 pi, beta0 / 2 pi
+    // and b0.  Lane k holds N_k.
+    if (role == 0 || (!init_mode && role <= 2)) {
+        const double asum = wave_sum(lane < K ? p.alpha0 + nr : 0.0);
+        const int nslot = role == 0 ? 2 * K + 1 : (role == 1 ? 2 * K + 4 : K + 2);
+        for (int j0 = 0; j0 < nslot; j0 += 64) {
+            const int j = j0 + lane;
+            const double nk = __shfl(nr, j < K ? j : (j < 2 * K ? j - K : 0), 64);
+            if (j >= nslot) continue;
+            if (role == 2) {
+                const double y = log(j < K ? (p.beta0 + nk) / kTwoPi : (j == K ? p.beta0 / kTwoPi : p.b0));
+                if (j < K) sh.ln_bt[j] = y;
+                else if (j == K) sh.ln_b0pi = y;
+                else sh.ln_b0 = y;
+                continue;
+            }
+            double x = j < K ? p.alpha0 + nk : (j < 2 * K ? p.a0 + 0.5 * nk : asum);
+            if (j > 2 * K) x = j == 2 * K + 1 ? K * p.alpha0 : (j == 2 * K + 2 ? p.alpha0 : p.a0);
+            if (role == 0) {
+                const double y = dev_digamma(x);
+                if (j < K) {
+                    sh.ak[j] = x;
+                    sh.psi_ak[j] = y;
+                } else if (j < 2 * K) {
+                    sh.psi_a[j - K] = y;
+                } else {
+                    sh.psum = y;
+                }
+            } else {
+                const double y = dev_lgamma(x);
+                if (j < K) sh.lg_ak[j] = y;
+                else if (j < 2 * K) sh.lg_a[j - K] = y;
+                else if (j == 2 * K) sh.lg_asum = y;
+                else if (j == 2 * K + 1) sh.lg_ka0 = y;
+                else if (j == 2 * K + 2) sh.lg_alpha0 = y;
+                else sh.lg_a0 = y;
+            }
         }
-        if (tid == 256) sh.lg_asum = dev_lgamma(x);
-    } else if (!init_mode && tid == 320) {
-        sh.lg_prior = dev_lgamma(K * p.alpha0) - K * dev_lgamma(p.alpha0);
+    }
+
+    // first item, before the barrier: the update and everything of its bound term but E ln tau;
+    // its new state stays in registers until the commit
+    double nmv = 0.0, nbt = 0.0, nav = 0.0, nbv = 0.0;
+    double lbb = 0.0, tb = 0.0, ibt = 0.0, nkbt = 0.0, sq = 0.0, dm0 = 0.0;
+    bool fin0 = true;
+    if (has0) {
+        const double c = (double)c0;
+        const double m0p = m00 - c;
+        const double bt = p.beta0 + N0;
+        const double mp = (p.beta0 * m0p + T10) / bt;
+        const double mm = c + mp;
+        const double aa = p.a0 + 0.5 * N0;
+        double bb = p.b0 + 0.5 * (T20 + p.beta0 * m0p * m0p - bt * mp * mp);
+        if (bb < p.b0) bb = p.b0;
+        nmv = mm;
+        nbt = bt;
+        nav = aa;
+        nbv = bb;
+        lbb = log(bb);
+        ibt = 1.0 / bt;
+        if (!init_mode) {
+            tb = aa / bb;
+            nkbt = N0 / bt;
+            sq = T20 - 2.0 * mp * T10 + N0 * mp * mp;  // sum r (x - m)^2
+            if (sq < 0.0) sq = 0.0;
+            dm0 = mp - m0p;                            // m - m0
+        }
+        coef_hq(v, q0, mm, aa, bb);
+        fin0 = isfinite(mm) && isfinite(bb) && isfinite(T20);
     }
     __syncthreads();
-    const double half_ln_b0 = 0.5 * log(p.beta0 / kTwoPi);
-    const double prior_const = half_ln_b0 + p.a0 * log(p.b0) - dev_lgamma(p.a0);
+
+    const double prior_const = init_mode ? 0.0 : 0.5 * sh.ln_b0pi + p.a0 * sh.ln_b0 - sh.lg_a0;
     double acc = 0.0;
-    int bad = 0;
-    // the new state of this thread's items stays in registers until the commit
+    int bad = !fin0;
+    if (has0) {
+        const double elt = sh.psi_a[k0] - lbb;
+        if (!isfinite(elt)) bad = 1;
+        if (!init_mode) {
+            const double aa = nav;
+            acc += 0.5 * (N0 * (elt - kLn2Pi) - tb * sq - nkbt);
+            acc += prior_const + 0.5 * elt - 0.5 * p.beta0 * (tb * dm0 * dm0 + ibt) + (p.a0 - 1.0) * elt - p.b0 * tb;
+            acc -= 0.5 * sh.ln_bt[k0] + 0.5 * elt - 0.5 + aa * lbb - sh.lg_a[k0] + (aa - 1.0) * elt - aa;
+        }
+        sh.tmp[q0] = 0.5 * (elt - kLn2Pi - ibt);
+    }
+    // further items (K G > 1024), after the barrier; their new state is staged in nm, nbeta, na, nb
     constexpr int kItems = kMaxKG / kMBlock;
-    double nmv[kItems], nbt[kItems], nav[kItems], nbv[kItems];
 #pragma unroll
-    for (int it = 0; it < kItems; ++it) {
+    for (int it = 1; it < kItems; ++it) {
         const int q = tid + it * kMBlock;
         if (q >= KG) break;
         const int k = q / G, g = q - k * G;
-        const double Nk = sh.nk[k];
+        const double Nk = total(v, k);
         const double T1q = total(v, K + q), T2q = total(v, K + KG + q);
         const double c = (double)v.mf[q];
         const double m0p = v.m0[g] - c;
@@ -264,38 +361,52 @@ __device__ __forceinline__ void mstep_one(const Shape &s, const Bufs &bf, const 
         const double aa = p.a0 + 0.5 * Nk;
         double bb = p.b0 + 0.5 * (T2q + p.beta0 * m0p * m0p - bt * mp * mp);
         if (bb < p.b0) bb = p.b0;
-        nmv[it] = mm;
-        nbt[it] = bt;
-        nav[it] = aa;
-        nbv[it] = bb;
+        v.nm[q] = mm;
+        v.nbeta[q] = bt;
+        v.na[q] = aa;
+        v.nb[q] = bb;
         const double elt = sh.psi_a[k] - log(bb);
-        const double tb = aa / bb;
+        const double tbq = aa / bb;
         if (!init_mode) {
-            double sq = T2q - 2.0 * mp * T1q + Nk * mp * mp;  // sum r (x - m)^2
-            if (sq < 0.0) sq = 0.0;
-            const double dm0 = mp - m0p;                        // m - m0
-            acc += 0.5 * (Nk * (elt - kLn2Pi) - tb * sq - Nk / bt);
-            acc += prior_const + 0.5 * elt - 0.5 * p.beta0 * (tb * dm0 * dm0 + 1.0 / bt) + (p.a0 - 1.0) * elt
-                   - p.b0 * tb;
+            double sqq = T2q - 2.0 * mp * T1q + Nk * mp * mp;
+            if (sqq < 0.0) sqq = 0.0;
+            const double dmq = mp - m0p;
+            acc += 0.5 * (Nk * (elt - kLn2Pi) - tbq * sqq - Nk / bt);
+            acc += prior_const + 0.5 * elt - 0.5 * p.beta0 * (tbq * dmq * dmq + 1.0 / bt) + (p.a0 - 1.0) * elt
+                   - p.b0 * tbq;
             acc -= 0.5 * sh.ln_bt[k] + 0.5 * elt - 0.5 + aa * log(bb) - sh.lg_a[k] + (aa - 1.0) * elt - aa;
         }
         sh.tmp[q] = coef_item(v, q, mm, bt, aa, bb, elt);
         if (!isfinite(mm) || !isfinite(bb) || !isfinite(elt) || !isfinite(T2q)) bad = 1;
     }
     if (bad) atomicOr(&sh.bad, 1);
-    __syncthreads();
-    coef_rows(v, sh, &p, !init_mode);
-    {
+    if (!init_mode) {
+        if (role == 0 && lane < K) {  // the q(pi) terms of the bound
+            const double ak = sh.ak[lane], elnpi = sh.psi_ak[lane] - sh.psum;
+            sh.term_k[lane] = nr * elnpi + (p.alpha0 - 1.0) * elnpi + sh.lg_ak[lane] - (ak - 1.0) * elnpi;
+        }
         const double ws = wave_sum(acc);
-        if ((tid & 63) == 0) sh.red[tid >> 6] = ws;
-        __syncthreads();
-        if (tid == 0)
-            for (int w = 1; w < kMBlock / 64; ++w) sh.red[0] += sh.red[w];
-        __syncthreads();
+        if (lane == 0) sh.red[tid >> 6] = ws;
     }
+    __syncthreads();
+
+    // c_k in every wave; the bound in thread 0 beside them
+    coef_rows(v, sh);
+    double L = 0.0;
+    if (tid == 0 && !init_mode) {
+        double r = sh.red[0];
+        for (int w = 1; w < kMBlock / 64; ++w) r += sh.red[w];
+        L = r + Hq;  // + H, the entropy of the responsibilities
+        const double lg_prior = sh.lg_ka0 - K * sh.lg_alpha0;
+        L += lg_prior - sh.lg_asum;
+        for (int k = 0; k < K; ++k) L += sh.term_k[k];
+        if (!isfinite(L)) sh.bad = 1;
+    }
+    __syncthreads();
+    const bool failed = sh.bad != 0;
     if (tid == 0) {
         if (init_mode) {
-            if (!sh.bad) {
+            if (!failed) {
                 ctl->sweeps = 0;
                 ctl->call_sweeps = 0;
                 ctl->converged = 0;
@@ -304,35 +415,31 @@ __device__ __forceinline__ void mstep_one(const Shape &s, const Bufs &bf, const 
             } else {
                 ctl->numeric = 1;
             }
+        } else if (failed) {
+            ctl->numeric = 1;
         } else {
-            double L = sh.red[0] + total(v, K + 2 * KG);  // + H, the entropy of the responsibilities
-            L += sh.lg_prior - sh.lg_asum;
-            for (int k = 0; k < K; ++k) L += sh.term_k[k];
-            if (!isfinite(L)) sh.bad = 1;
-            if (sh.bad) {
-                ctl->numeric = 1;
-            } else {
-                const int t = ctl->call_sweeps + 1;
-                if (t >= 2 && fabs(L - ctl->elbo) <= ctl->tol * fabs(L)) ctl->converged = 1;
-                ctl->elbo_prev = ctl->elbo;
-                ctl->elbo = L;
-                v.hist[(t - 1) % s.hist_cap] = L;
-                ctl->call_sweeps = t;
-                ctl->sweeps += 1;
-            }
+            const int t = ctl->call_sweeps + 1;
+            if (t >= 2 && fabs(L - ctl->elbo) <= ctl->tol * fabs(L)) ctl->converged = 1;
+            ctl->elbo_prev = ctl->elbo;
+            ctl->elbo = L;
+            v.hist[(t - 1) % s.hist_cap] = L;
+            ctl->call_sweeps = t;
+            ctl->sweeps += 1;
         }
     }
-    __syncthreads();
-    if (sh.bad) return;
-    if (tid < K) v.alpha[tid] = v.nalpha[tid];
-#pragma unroll
-    for (int it = 0; it < kItems; ++it) {
-        const int q = tid + it * kMBlock;
-        if (q >= KG) break;
-        v.m[q] = nmv[it];
-        v.beta[q] = nbt[it];
-        v.a[q] = nav[it];
-        v.b[q] = nbv[it];
+    if (failed) return;
+    if (tid < K) v.alpha[tid] = sh.ak[tid];
+    if (has0) {
+        v.m[q0] = nmv;
+        v.beta[q0] = nbt;
+        v.a[q0] = nav;
+        v.b[q0] = nbv;
+    }
+    for (int q = tid + kMBlock; q < KG; q += kMBlock) {
+        v.m[q] = v.nm[q];
+        v.beta[q] = v.nbeta[q];
+        v.a[q] = v.na[q];
+        v.b[q] = v.nb[q];
     }
 }
 
