@@ -14,7 +14,9 @@ namespace {
 constexpr double kLn2Pi = 1.8378770664093454835606594728112;
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr int kRedBlock = 1024;  // k_reduce: 16 waves per 64 statistics
-constexpr int kMBlock = 1024;    // k_mstep, k_coef: one (k, g) item per thread up to K G = 1024
+constexpr int kMBlock = 1024;    // k_mstep (one dataset), k_coef: one (k, g) item per thread up to K G = 1024
+constexpr int kMBatchBlock = 512;  // k_mstep_batch: a batch's datasets are small; 512 threads leave
+                                   // the update its registers and fit four workgroups per CU
 
 // Sum over the 64 lanes of a wave with a fixed butterfly (same order every run).
 __device__ __forceinline__ double wave_sum(double v)
@@ -24,8 +26,9 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+template <int NT>
 struct MShared {
-    double red[kMBlock / 64];
+    double red[NT / 64];
     double ak[kMaxK], psi_ak[kMaxK], lg_ak[kMaxK], term_k[kMaxK];
     double psi_a[kMaxK], lg_a[kMaxK], ln_bt[kMaxK];  // per component: digamma, lgamma of a_kg; ln(beta_kg / 2 pi)
     double tmp[kMaxKG];
@@ -124,11 +127,12 @@ __device__ __forceinline__ double coef_item(const View &v, int q, double mm, dou
 }
 
 // c_k from the per-(k,g) parts in LDS: wave w sums subpopulations w, w+16, ...
-__device__ __forceinline__ void coef_rows(const View &v, MShared &sh)
+template <int NT>
+__device__ __forceinline__ void coef_rows(const View &v, MShared<NT> &sh)
 {
     const int G = v.G, K = v.K;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int k = wv; k < K; k += kMBlock / 64) {
+    for (int k = wv; k < K; k += NT / 64) {
         double x = 0.0;
         for (int g = lane; g < G; g += 64) x += sh.tmp[k * G + g];
         x = wave_sum(x);
@@ -205,7 +209,7 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce(Shape s, Bufs bf, int init
 // Coefficients of the E-step from the committed state (after set_state).
 __global__ __launch_bounds__(kMBlock) void k_coef(Shape s, Bufs bf)
 {
-    __shared__ MShared sh;
+    __shared__ MShared<kMBlock> sh;
     const View v = view(s, bf, blockIdx.x);
     const int tid = threadIdx.x, K = v.K, KG = K * v.G;
     if (tid == 0) sh.bad = 0;
@@ -232,13 +236,14 @@ __global__ __launch_bounds__(kMBlock) void k_coef(Shape s, Bufs bf)
 // then the lower bound at the new q(pi), q(mu, tau) with the entropy H of the
 // responsibilities.  A non-finite value leaves the state untouched and raises
 // ctl->numeric.
+template <int NT>
 __device__ __forceinline__ void mstep_one(const Shape &s, const Bufs &bf, const Prior &p, int init_mode, int bi,
-                                          MShared &sh)
+                                          MShared<NT> &sh)
 {
     const View v = view(s, bf, bi);
     Ctl *ctl = v.ctl;
     const int G = v.G, K = v.K, KG = K * G, tid = threadIdx.x;
-    const int lane = tid & 63, role = kMBlock / 64 - 1 - (tid >> 6);  // wave 15 - role
+    const int lane = tid & 63, role = NT / 64 - 1 - (tid >> 6);  // roles from the last wave down
     // Every statistic this thread reads is requested at once, before the skip test, so that one
     // memory latency covers them all: its first item (q = tid; clamped indices where the thread
     // has none), the count of its lane's subpopulation, the entropy.
@@ -254,12 +259,12 @@ __device__ __forceinline__ void mstep_one(const Shape &s, const Bufs &bf, const 
     const double nr = sum_total(v, lR), Hq = sum_total(v, lH);
     if (tid == 0) sh.bad = 0;
 
-    // Special functions, one function per wave and one argument per lane, in the top three waves
-    // (which hold no items while K G <= 832), while the item threads run the parts of their updates
-    // that do not need them.  Digamma (wave 15) and lgamma (wave 14) of alpha_k = alpha0 + N_k,
-    // of a_kg = a0 + N_k / 2 (the same for every gene of a subpopulation) and of sum(alpha); the
-    // lgamma wave adds K alpha0, alpha0 and a0.  Logarithms (wave 13) of beta_kg / 2 pi, beta0 / 2 pi
-    // and b0.  Lane k holds N_k.
+    // Special functions, one function per wave and one argument per lane, in the last three waves
+    // (which hold no items while K G <= NT - 192), while the item threads run the parts of their
+    // updates that do not need them.  Digamma (last wave) and lgamma (the one before) of
+    // alpha_k = alpha0 + N_k, of a_kg = a0 + N_k / 2 (the same for every gene of a subpopulation) and
+    // of sum(alpha); the lgamma wave adds K alpha0, alpha0 and a0.  Logarithms (third from last) of
+    // beta_kg / 2 pi, beta0 / 2 pi and b0.  Lane k holds N_k.
     if (role == 0 || (!init_mode && role <= 2)) {
         const double asum = wave_sum(lane < K ? p.alpha0 + nr : 0.0);
         const int nslot = role == 0 ? 2 * K + 1 : (role == 1 ? 2 * K + 4 : K + 2);
@@ -344,12 +349,8 @@ __device__ __forceinline__ void mstep_one(const Shape &s, const Bufs &bf, const 
         }
         sh.tmp[q0] = 0.5 * (elt - kLn2Pi - ibt);
     }
-    // further items (K G > 1024), after the barrier; their new state is staged in nm, nbeta, na, nb
-    constexpr int kItems = kMaxKG / kMBlock;
-#pragma unroll
-    for (int it = 1; it < kItems; ++it) {
-        const int q = tid + it * kMBlock;
-        if (q >= KG) break;
+    // further items (K G > NT), after the barrier; their new state is staged in nm, nbeta, na, nb
+    for (int q = tid + NT; q < KG; q += NT) {
         const int k = q / G, g = q - k * G;
         const double Nk = total(v, k);
         const double T1q = total(v, K + q), T2q = total(v, K + KG + q);
@@ -395,7 +396,7 @@ __device__ __forceinline__ void mstep_one(const Shape &s, const Bufs &bf, const 
     double L = 0.0;
     if (tid == 0 && !init_mode) {
         double r = sh.red[0];
-        for (int w = 1; w < kMBlock / 64; ++w) r += sh.red[w];
+        for (int w = 1; w < NT / 64; ++w) r += sh.red[w];
         L = r + Hq;  // + H, the entropy of the responsibilities
         const double lg_prior = sh.lg_ka0 - K * sh.lg_alpha0;
         L += lg_prior - sh.lg_asum;
@@ -435,7 +436,7 @@ __device__ __forceinline__ void mstep_one(const Shape &s, const Bufs &bf, const 
         v.a[q0] = nav;
         v.b[q0] = nbv;
     }
-    for (int q = tid + kMBlock; q < KG; q += kMBlock) {
+    for (int q = tid + NT; q < KG; q += NT) {
         v.m[q] = v.nm[q];
         v.beta[q] = v.nbeta[q];
         v.a[q] = v.na[q];
@@ -443,16 +444,20 @@ __device__ __forceinline__ void mstep_one(const Shape &s, const Bufs &bf, const 
     }
 }
 
+// a single dataset
 __global__ __launch_bounds__(kMBlock) void k_mstep(Shape s, Bufs bf, Prior p, int init_mode)
 {
-    __shared__ MShared sh;
-    if (s.B == 1) {  // a single dataset: no work list
-        mstep_one(s, bf, p, init_mode, 0, sh);
-        return;
-    }
+    __shared__ MShared<kMBlock> sh;
+    mstep_one<kMBlock>(s, bf, p, init_mode, 0, sh);
+}
+
+// a batch: the workgroups loop over the datasets on the work list
+__global__ __launch_bounds__(kMBatchBlock) void k_mstep_batch(Shape s, Bufs bf, Prior p, int init_mode)
+{
+    __shared__ MShared<kMBatchBlock> sh;
     const int nds = n_active_datasets(s, bf);
     for (int slot = blockIdx.x; slot < nds; slot += gridDim.x) {
-        mstep_one(s, bf, p, init_mode, bf.act_ds[slot], sh);
+        mstep_one<kMBatchBlock>(s, bf, p, init_mode, bf.act_ds[slot], sh);
         __syncthreads();  // sh is rewritten by the next dataset
     }
 }
@@ -466,7 +471,10 @@ hipError_t launch_reduce(const Shape &s, const Bufs &b, int init_mode, hipStream
 
 hipError_t launch_mstep(const Shape &s, const Bufs &b, const Prior &p, int init_mode, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mstep, dim3(s.dgrid), dim3(kMBlock), 0, st, s, b, p, init_mode);
+    if (s.B == 1)
+        hipLaunchKernelGGL(k_mstep, dim3(1), dim3(kMBlock), 0, st, s, b, p, init_mode);
+    else
+        hipLaunchKernelGGL(k_mstep_batch, dim3(s.dgrid), dim3(kMBatchBlock), 0, st, s, b, p, init_mode);
     return hipGetLastError();
 }
 
