@@ -397,6 +397,9 @@ cavi_status sweep_n(Handle *h, int32_t n, double *elbo_host)
     if (!all_have_state(h)) return fail(CAVI_E_STATE, "no state: call init_standard or set_state");
     cavi_status rs = refresh_coef(h);
     if (rs == CAVI_OK) rs = autotune(h);  // before the control blocks are set for this call
+    // every graph size is captured at the first call, so that no later call waits for a capture
+    // (a few hundred microseconds of host work) before its first launch
+    for (int gi = 0; gi < kNumGraphs && rs == CAVI_OK; ++gi) rs = ensure_graph(h, gi);
     if (rs != CAVI_OK) return rs;
     const int cap = h->s.hist_cap;
     int done = 0;

@@ -86,7 +86,7 @@ struct Bufs {
     const int32_t *chunk_ds;  // nchunk: dataset of each global chunk
     double *alpha;        // B x Kmax          q(pi)
     double *m, *beta, *a, *b;  // B x Kmax x G  q(mu, tau)
-    double *nalpha, *nm, *nbeta, *na, *nb;  // next-state staging
+    double *nm, *nbeta, *na, *nb;  // next-state staging (update items past the block size)
     double *m0;           // B x G prior centre
     float *cc;            // B x Kmax         c_k of the row log-likelihood
     float *hq;            // B x Kmax x G x 2  (h, q): u = h x + q, l = c - sum u^2

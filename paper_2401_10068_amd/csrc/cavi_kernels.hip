@@ -815,7 +815,7 @@ size_t workspace_bytes(const Shape &s)
     const size_t nblk = s.nchunk;  // per-chunk maxima and weight sums (initialisation)
     size_t n = 0;
     n += al(B * sizeof(Ds)) + al((size_t)s.nchunk * 4);
-    n += 2 * al(K * 8);                // alpha, nalpha
+    n += al(K * 8);                    // alpha
     n += 8 * al(KG * 8);               // m beta a b, nm nbeta na nb
     n += al(B * G * 8);                // m0
     n += al(K * 4) + al(2 * KG * 4) + 2 * al(KG * 4);  // cc, hq, mf, seeds
@@ -843,7 +843,6 @@ void carve(const Shape &s, void *ws, Bufs &b)
     b.ds = (const Ds *)take(B * sizeof(Ds));
     b.chunk_ds = (const int32_t *)take((size_t)s.nchunk * 4);
     b.alpha = (double *)take(K * 8);
-    b.nalpha = (double *)take(K * 8);
     b.m = (double *)take(KG * 8);
     b.beta = (double *)take(KG * 8);
     b.a = (double *)take(KG * 8);

@@ -42,7 +42,7 @@ struct MShared {
 struct View {
     int K, G;
     double *alpha, *m, *beta, *a, *b;
-    double *nalpha, *nm, *nbeta, *na, *nb;
+    double *nm, *nbeta, *na, *nb;
     const double *m0;
     float *cc, *hq, *mf;
     const double *totals;  // nsplit x smax: the sums of the dataset's chunk ranges
@@ -60,7 +60,6 @@ __device__ __forceinline__ View view(const Shape &s, const Bufs &bf, int bi)
     v.K = d.K;
     v.G = s.G;
     v.alpha = bf.alpha + kb;
-    v.nalpha = bf.nalpha + kb;
     v.m = bf.m + kg;
     v.beta = bf.beta + kg;
     v.a = bf.a + kg;
