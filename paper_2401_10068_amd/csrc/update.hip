@@ -253,6 +253,9 @@ __device__ __forceinline__ void mstep_one(const Shape &s, const Bufs &bf, const 
     const Tot lR = load_total(v, lane < K ? lane : 0), lH = load_total(v, K + 2 * KG);
     const float c0 = v.mf[qc];
     const double m00 = v.m0[qc - kc * G];
+    // the control-block fields thread 0 updates at the end (only it writes them), read now as well
+    const int cs0 = ctl->call_sweeps, sw0 = ctl->sweeps;
+    const double elbo0 = ctl->elbo, tol0 = ctl->tol;
     if (!init_mode && sweep_skipped(ctl)) return;
     const double N0 = sum_total(v, lN), T10 = sum_total(v, lT1), T20 = sum_total(v, lT2);
     const double nr = sum_total(v, lR), Hq = sum_total(v, lH);
@@ -418,13 +421,13 @@ __device__ __forceinline__ void mstep_one(const Shape &s, const Bufs &bf, const 
         } else if (failed) {
             ctl->numeric = 1;
         } else {
-            const int t = ctl->call_sweeps + 1;
-            if (t >= 2 && fabs(L - ctl->elbo) <= ctl->tol * fabs(L)) ctl->converged = 1;
-            ctl->elbo_prev = ctl->elbo;
+            const int t = cs0 + 1;
+            if (t >= 2 && fabs(L - elbo0) <= tol0 * fabs(L)) ctl->converged = 1;
+            ctl->elbo_prev = elbo0;
             ctl->elbo = L;
             v.hist[(t - 1) % s.hist_cap] = L;
             ctl->call_sweeps = t;
-            ctl->sweeps += 1;
+            ctl->sweeps = sw0 + 1;
         }
     }
     if (failed) return;
