@@ -150,7 +150,11 @@ cavi_status cavi_probe_read(const float *x_dev, int64_t n, float *out_dev, int32
  * launches per sweep, each dataset with its own convergence test).  The same
  * kernels and the same per-dataset reduction order as a single-dataset
  * handle, so a dataset's results are bitwise those of a single handle over
- * its rows.
+ * its rows when both run the same E-step arithmetic: the E-step is compiled
+ * for the handle's largest K, and for G in {16, 32, 48, 64, 96, 128} a
+ * largest K up to 8 and one in 9..16 round differently (a dataset with K up
+ * to 8 in a batch whose largest K is above 8 agrees with a single handle to
+ * rounding, not bitwise).
  *   - x_dev holds the rows of all datasets concatenated (dataset 0 first),
  *     sum(N) x G FP32, device memory, caller-owned, 16-byte aligned.
  *   - N and K are HOST arrays of B entries; each dataset obeys the

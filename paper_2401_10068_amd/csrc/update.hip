@@ -28,7 +28,7 @@ __device__ __forceinline__ double wave_sum(double v)
 
 template <int NT>
 struct MShared {
-    double red[NT / 64];
+    double red[kMaxKG / 64];  // the bound's item terms, one sum per group of 64 items (see mstep_one)
     double ak[kMaxK], psi_ak[kMaxK], lg_ak[kMaxK], term_k[kMaxK];
     double psi_a[kMaxK], lg_a[kMaxK], ln_bt[kMaxK];  // per component: digamma, lgamma of a_kg; ln(beta_kg / 2 pi)
     double tmp[kMaxKG];
@@ -351,45 +351,56 @@ __device__ __forceinline__ void mstep_one(const Shape &s, const Bufs &bf, const 
         }
         sh.tmp[q0] = 0.5 * (elt - kLn2Pi - ibt);
     }
-    // further items (K G > NT), after the barrier; their new state is staged in nm, nbeta, na, nb
-    for (int q = tid + NT; q < KG; q += NT) {
-        const int k = q / G, g = q - k * G;
-        const double Nk = total(v, k);
-        const double T1q = total(v, K + q), T2q = total(v, K + KG + q);
-        const double c = (double)v.mf[q];
-        const double m0p = v.m0[g] - c;
-        const double bt = p.beta0 + Nk;
-        const double mp = (p.beta0 * m0p + T1q) / bt;
-        const double mm = c + mp;
-        const double aa = p.a0 + 0.5 * Nk;
-        double bb = p.b0 + 0.5 * (T2q + p.beta0 * m0p * m0p - bt * mp * mp);
-        if (bb < p.b0) bb = p.b0;
-        v.nm[q] = mm;
-        v.nbeta[q] = bt;
-        v.na[q] = aa;
-        v.nb[q] = bb;
-        const double elt = sh.psi_a[k] - log(bb);
-        const double tbq = aa / bb;
-        if (!init_mode) {
-            double sqq = T2q - 2.0 * mp * T1q + Nk * mp * mp;
-            if (sqq < 0.0) sqq = 0.0;
-            const double dmq = mp - m0p;
-            acc += 0.5 * (Nk * (elt - kLn2Pi) - tbq * sqq - Nk / bt);
-            acc += prior_const + 0.5 * elt - 0.5 * p.beta0 * (tbq * dmq * dmq + 1.0 / bt) + (p.a0 - 1.0) * elt
-                   - p.b0 * tbq;
-            acc -= 0.5 * sh.ln_bt[k] + 0.5 * elt - 0.5 + aa * log(bb) - sh.lg_a[k] + (aa - 1.0) * elt - aa;
-        }
-        sh.tmp[q] = coef_item(v, q, mm, bt, aa, bb, elt);
-        if (!isfinite(mm) || !isfinite(bb) || !isfinite(elt) || !isfinite(T2q)) bad = 1;
-    }
-    if (bad) atomicOr(&sh.bad, 1);
+    // The bound's item terms are summed per group of 64 consecutive items (a wave sum each), and
+    // the groups in item order, so that the sum does not depend on the block size: a dataset in a
+    // batch (512-thread blocks) gets the bits of a single handle (1024).
     if (!init_mode) {
-        if (role == 0 && lane < K) {  // the q(pi) terms of the bound
-            const double ak = sh.ak[lane], elnpi = sh.psi_ak[lane] - sh.psum;
-            sh.term_k[lane] = nr * elnpi + (p.alpha0 - 1.0) * elnpi + sh.lg_ak[lane] - (ak - 1.0) * elnpi;
-        }
         const double ws = wave_sum(acc);
         if (lane == 0) sh.red[tid >> 6] = ws;
+    }
+    // further items (K G > NT), after the barrier; their new state is staged in nm, nbeta, na, nb
+    for (int base = NT; base < KG; base += NT) {
+        const int q = base + tid;
+        double accq = 0.0;
+        if (q < KG) {
+            const int k = q / G, g = q - k * G;
+            const double Nk = total(v, k);
+            const double T1q = total(v, K + q), T2q = total(v, K + KG + q);
+            const double c = (double)v.mf[q];
+            const double m0p = v.m0[g] - c;
+            const double bt = p.beta0 + Nk;
+            const double mp = (p.beta0 * m0p + T1q) / bt;
+            const double mm = c + mp;
+            const double aa = p.a0 + 0.5 * Nk;
+            double bb = p.b0 + 0.5 * (T2q + p.beta0 * m0p * m0p - bt * mp * mp);
+            if (bb < p.b0) bb = p.b0;
+            v.nm[q] = mm;
+            v.nbeta[q] = bt;
+            v.na[q] = aa;
+            v.nb[q] = bb;
+            const double elt = sh.psi_a[k] - log(bb);
+            const double tbq = aa / bb;
+            if (!init_mode) {
+                double sqq = T2q - 2.0 * mp * T1q + Nk * mp * mp;
+                if (sqq < 0.0) sqq = 0.0;
+                const double dmq = mp - m0p;
+                accq += 0.5 * (Nk * (elt - kLn2Pi) - tbq * sqq - Nk / bt);
+                accq += prior_const + 0.5 * elt - 0.5 * p.beta0 * (tbq * dmq * dmq + 1.0 / bt) + (p.a0 - 1.0) * elt
+                        - p.b0 * tbq;
+                accq -= 0.5 * sh.ln_bt[k] + 0.5 * elt - 0.5 + aa * log(bb) - sh.lg_a[k] + (aa - 1.0) * elt - aa;
+            }
+            sh.tmp[q] = coef_item(v, q, mm, bt, aa, bb, elt);
+            if (!isfinite(mm) || !isfinite(bb) || !isfinite(elt) || !isfinite(T2q)) bad = 1;
+        }
+        if (!init_mode) {
+            const double ws = wave_sum(accq);
+            if (lane == 0 && base + (tid & ~63) < KG) sh.red[q >> 6] = ws;
+        }
+    }
+    if (bad) atomicOr(&sh.bad, 1);
+    if (!init_mode && role == 0 && lane < K) {  // the q(pi) terms of the bound
+        const double ak = sh.ak[lane], elnpi = sh.psi_ak[lane] - sh.psum;
+        sh.term_k[lane] = nr * elnpi + (p.alpha0 - 1.0) * elnpi + sh.lg_ak[lane] - (ak - 1.0) * elnpi;
     }
     __syncthreads();
 
@@ -398,7 +409,7 @@ __device__ __forceinline__ void mstep_one(const Shape &s, const Bufs &bf, const 
     double L = 0.0;
     if (tid == 0 && !init_mode) {
         double r = sh.red[0];
-        for (int w = 1; w < NT / 64; ++w) r += sh.red[w];
+        for (int w = 1; w < (KG + 63) / 64; ++w) r += sh.red[w];
         L = r + Hq;  // + H, the entropy of the responsibilities
         const double lg_prior = sh.lg_ka0 - K * sh.lg_alpha0;
         L += lg_prior - sh.lg_asum;

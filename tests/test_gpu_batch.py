@@ -1,5 +1,7 @@
 """Batched CAVI through the C ABI: each dataset of a batch gives bitwise the
-results of a single-dataset handle over its rows, and matches the oracle."""
+results of a single-dataset handle over its rows (both running the same E-step
+arithmetic: for the tiled widths of G, the batch's largest K and the dataset's K
+both at most 8, or both in 9..16), and matches the oracle."""
 import numpy as np
 import pytest
 
@@ -169,3 +171,30 @@ def test_batch_run_work_lists_bitwise(torch_cuda, B):
         if st is not None:
             for a, r in zip(got[b], st):
                 assert np.array_equal(a, r), b
+
+
+@pytest.mark.parametrize("G,Ks", [(48, [16, 12, 9]), (96, [9, 12, 10])])
+def test_batch_bound_bitwise_above_the_batch_block(torch_cuda, G, Ks):
+    """Datasets of more than 512 (k, g) items (up to 1,152): the batch update's 512-thread blocks
+    give a thread two or three of them where a single handle's 1024-thread block gives one or two.
+    The bound is summed per group of 64 items, so the runs to convergence still stop at the same
+    sweep with bitwise the same bound, and end in bitwise the same states.  Every K is above 8, as
+    is each batch's largest, so batch and single handles share the E-step's arithmetic."""
+    from paper_2401_10068_amd.cavi import Cavi, CaviBatch
+
+    Ns = [3000, 5000, 2500]
+    xs, m0 = make_batch(31, Ns, Ks, G)
+    bt = CaviBatch(torch_cuda.from_numpy(np.concatenate(xs)).cuda(), Ns, Ks, m0=m0)
+    bt.init_standard(5)
+    sw, el, _ = bt.run(400, 1e-6)
+    got = [bt.get_state(b) for b in range(len(Ns))]
+    bt.close()
+    for b, (X, K) in enumerate(zip(xs, Ks)):
+        cx = Cavi(torch_cuda.from_numpy(X).cuda(), K, m0=m0[b])
+        cx.init_standard(5 + b)
+        n, L, _ = cx.run(400, 1e-6)
+        st = cx.get_state()
+        cx.close()
+        assert n == sw[b] and L == el[b], (b, n, sw[b], L, el[b])
+        for a, r in zip(got[b], st):
+            assert np.array_equal(a, r), b
