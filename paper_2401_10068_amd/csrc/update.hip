@@ -13,7 +13,9 @@ namespace {
 
 constexpr double kLn2Pi = 1.8378770664093454835606594728112;
 constexpr double kTwoPi = 6.283185307179586476925286766559;
-constexpr int kRedBlock = 1024;  // k_reduce: 16 waves per 64 statistics
+constexpr int kRedBlock = 1024;  // k_reduce: 16 waves per 64 statistics (a single dataset)
+constexpr int kRedBatchBlock = 256;  // k_reduce for batches: 4 waves running the 16 wave slots
+constexpr int kRedBatchGrid = 2048;  // datasets a batch's reduction takes at once
 constexpr int kMBlock = 1024;    // k_mstep (one dataset), k_coef: one (k, g) item per thread up to K G = 1024
 constexpr int kMBatchBlock = 512;  // k_mstep_batch: a batch's datasets are small; 512 threads leave
                                    // the update its registers and fit four workgroups per CU
@@ -151,11 +153,16 @@ __device__ __forceinline__ void coef_rows(const View &v, MShared<NT> &sh)
 // contiguous 1/16 of the range's chunks (4 interleaved accumulators), then the 16 wave sums are added
 // in wave order.  The ranges spread a large dataset over Z workgroups per 64 statistics; the update
 // adds them.
-__global__ __launch_bounds__(kRedBlock) void k_reduce(Shape s, Bufs bf, int init_mode)
+// The sixteen wave slots of the order above are taken by NT / 64 waves, each running 1024 / NT
+// slots in turn (one for a single dataset's 1024-thread blocks; four for a batch's 256-thread
+// blocks, whose datasets are mostly a few chunks each), so both give the same sums.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_reduce(Shape s, Bufs bf, int init_mode)
 {
-    __shared__ double part[kRedBlock / 64][64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int nw = kRedBlock / 64;
+    constexpr int nw = kRedBlock / 64;    // wave slots of the summation order
+    constexpr int per = nw / (NT / 64);   // slots per wave
+    __shared__ double part[nw][64];
+    const int lane = threadIdx.x & 63, rw = threadIdx.x >> 6;
     const int i = blockIdx.x * 64 + lane;
     const int z = blockIdx.z;
     const int nds = n_active_datasets(s, bf);
@@ -169,34 +176,42 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce(Shape s, Bufs bf, int init
         // 32-bit products: a dataset has fewer than 2^31 rows, so fewer than 2^20 chunks
         const int r0 = (d.nchunk * z) / Z, r1 = (d.nchunk * (z + 1)) / Z;
         const int nr = r1 - r0;
-        const int c0 = (nr * wv) / nw, c1 = (nr * (wv + 1)) / nw;
-        const int n = c1 - c0, n4 = n & ~3;  // this wave's chunks; those in whole groups of four
         // lanes past the statistics read the last one (their sums are not stored)
-        const double *pp = bf.partials + (size_t)(d.chunk0 + r0 + c0) * s.Smax + min(i, S - 1);
-        // chunks in batches of eight loads in flight (indices clamped to the wave's last chunk);
-        // the first batch is requested before the skip test
+        const double *base = bf.partials + (size_t)(d.chunk0 + r0) * s.Smax + min(i, S - 1);
+        // a slot's chunks in batches of eight loads in flight (indices clamped to the slot's last
+        // chunk); the first batch of the wave's first slot is requested before the skip test
         double L[8];
-        auto load8 = [&](int b0) {
+        auto load8 = [&](const double *pp, int n, int b0) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) L[k] = pp[(size_t)min(b0 + k, n - 1) * s.Smax];
         };
-        if (n > 0) load8(0);
+        int c0 = (nr * (rw * per)) / nw, n = (nr * (rw * per + 1)) / nw - c0;
+        if (n > 0) load8(base + (size_t)c0 * s.Smax, n, 0);
         if (!init_mode && sweep_skipped(bf.ctl + bi)) continue;
-        double q[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int b0 = 0; b0 < n; b0 += 8) {
-            if (b0 > 0) load8(b0);
-            // chunk t adds to accumulator t mod 4 while in a whole group of four, else to the first
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int t = b0 + k;
-                if (t < n4) q[k & 3] += L[k];
-                else if (t < n) q[0] += L[k];
+        for (int u = 0; u < per; ++u) {
+            const int wv = rw * per + u;  // the slot
+            if (u > 0) {
+                c0 = (nr * wv) / nw;
+                n = (nr * (wv + 1)) / nw - c0;
+                if (n > 0) load8(base + (size_t)c0 * s.Smax, n, 0);
             }
+            const int n4 = n & ~3;  // the slot's chunks in whole groups of four
+            const double *pp = base + (size_t)c0 * s.Smax;
+            double q[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int b0 = 0; b0 < n; b0 += 8) {
+                if (b0 > 0) load8(pp, n, b0);
+                // chunk t adds to accumulator t mod 4 while in a whole group of four, else to the first
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int t = b0 + k;
+                    if (t < n4) q[k & 3] += L[k];
+                    else if (t < n) q[0] += L[k];
+                }
+            }
+            part[wv][lane] = (q[0] + q[1]) + (q[2] + q[3]);
         }
-        const double acc = (q[0] + q[1]) + (q[2] + q[3]);
-        part[wv][lane] = acc;
         __syncthreads();
-        if (wv == 0 && i < S) {
+        if (rw == 0 && i < S) {
             double t = part[0][lane];
             for (int v = 1; v < nw; ++v) t += part[v][lane];
             bf.totals[((size_t)bi * red_split_max(s.Nmax) + z) * s.Smax + i] = t;
@@ -477,8 +492,11 @@ __global__ __launch_bounds__(kMBatchBlock) void k_mstep_batch(Shape s, Bufs bf, 
 
 hipError_t launch_reduce(const Shape &s, const Bufs &b, int init_mode, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce, dim3((s.Smax + 63) / 64, s.dgrid, red_split_max(s.Nmax)), dim3(kRedBlock), 0, st, s,
-                       b, init_mode);
+    const dim3 grid((s.Smax + 63) / 64, s.B == 1 ? 1 : std::min(s.B, kRedBatchGrid), red_split_max(s.Nmax));
+    if (s.B == 1)
+        hipLaunchKernelGGL(k_reduce<kRedBlock>, grid, dim3(kRedBlock), 0, st, s, b, init_mode);
+    else
+        hipLaunchKernelGGL(k_reduce<kRedBatchBlock>, grid, dim3(kRedBatchBlock), 0, st, s, b, init_mode);
     return hipGetLastError();
 }
 
