@@ -17,8 +17,9 @@ constexpr int kRedBlock = 1024;  // k_reduce: 16 waves per 64 statistics (a sing
 constexpr int kRedBatchBlock = 256;  // k_reduce for batches: 4 waves running the 16 wave slots
 constexpr int kRedBatchGrid = 2048;  // datasets a batch's reduction takes at once
 constexpr int kMBlock = 1024;    // k_mstep (one dataset), k_coef: one (k, g) item per thread up to K G = 1024
-constexpr int kMBatchBlock = 512;  // k_mstep_batch: a batch's datasets are small; 512 threads leave
-                                   // the update its registers and fit four workgroups per CU
+constexpr int kMBatchBlock = 256;  // k_mstep_batch: a batch's datasets are small; 256 threads leave
+                                   // the update its registers and fit three workgroups per CU
+constexpr int kMBatchGrid = 2048;  // datasets a batch's update takes at once
 
 // Sum over the 64 lanes of a wave with a fixed butterfly (same order every run).
 __device__ __forceinline__ double wave_sum(double v)
@@ -505,7 +506,8 @@ hipError_t launch_mstep(const Shape &s, const Bufs &b, const Prior &p, int init_
     if (s.B == 1)
         hipLaunchKernelGGL(k_mstep, dim3(1), dim3(kMBlock), 0, st, s, b, p, init_mode);
     else
-        hipLaunchKernelGGL(k_mstep_batch, dim3(s.dgrid), dim3(kMBatchBlock), 0, st, s, b, p, init_mode);
+        hipLaunchKernelGGL(k_mstep_batch, dim3(std::min(s.B, kMBatchGrid)), dim3(kMBatchBlock), 0, st, s, b, p,
+                           init_mode);
     return hipGetLastError();
 }
 
