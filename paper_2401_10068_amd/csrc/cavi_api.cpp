@@ -42,7 +42,6 @@ cavi_status fail(cavi_status st, const char *fmt, ...)
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
 constexpr int64_t kBatchChunkGrid = 2048;  // E-step workgroups of a batch launch
-constexpr int32_t kBatchDatasetGrid = 512;  // datasets a batch's reduction and update take at once
 
 cavi_status make_shape(int32_t B, const int64_t *N, const int32_t *K, int32_t G, int hist_cap, Shape &s,
                        std::vector<Ds> *ds)
@@ -74,7 +73,6 @@ cavi_status make_shape(int32_t B, const int64_t *N, const int32_t *K, int32_t G,
     s.hist_cap = hist_cap;
     // batches: capped grids that loop over the work lists (a single dataset: one workgroup per chunk)
     s.egrid = B > 1 ? (int32_t)std::min<int64_t>(nchunk, kBatchChunkGrid) : (int32_t)nchunk;
-    s.dgrid = B > 1 ? std::min(B, kBatchDatasetGrid) : 1;
     s.Ntot = ntot;
     s.Nmax = nmax;
     return CAVI_OK;

@@ -74,7 +74,6 @@ struct Shape {
     int32_t hist_cap;   // bounds kept per dataset
     int32_t schedule;   // tiled E-step schedule: 0 register-heavy, 1 register-light (autotuned)
     int32_t egrid;      // workgroups of an E-step launch (batches: a capped grid over the work list)
-    int32_t dgrid;      // workgroups per statistic block of the reduction and of the update (batches)
     int64_t Ntot;       // rows of all datasets
     int64_t Nmax;       // rows of the largest dataset
 };
